@@ -1,0 +1,187 @@
+"""Pins of the oracle's start solutions and path tracker.
+
+Only endpoints are pinned (the step sequence is a heuristic and parity-unpinned):
+* closed-form roots of unity and the mixed-radix path numbering;
+* f = g: every path stays at its start point;
+* decoupled f_i = x_i^{d_i} - c_i: closed-form path x_i(t)^{d_i} =
+  (gamma(1-t) + t c_i) / (gamma(1-t) + t), endpoint the d_i-th root of c_i on the
+  branch continued from the start point (argument unwrapped on a fine t grid);
+* n = 1: the set of endpoints equals numpy.roots;
+* Bezout count: B paths succeed with B distinct endpoints;
+* residual of polished endpoints is at the rounding level;
+* forced failures: a path to infinity, NaN start, h_min > h_init, max_steps,
+  singular Jacobian.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1505_00383_amd import synth
+from tests.exact import frc
+
+U = {1: 2.0 ** -53, 2: 2.0 ** -104, 4: 2.0 ** -208}
+
+
+def _cx(x):
+    """[..., 2, L] -> complex (hi limbs)."""
+    return x[..., 0, 0] + 1j * x[..., 1, 0]
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_start_solutions_closed_form(L):
+    deg = np.array([2, 3, 2, 3], dtype=np.int32)
+    B = int(np.prod(deg))
+    seen = set()
+    for p in range(B):
+        x = oracle.start_solution(L, deg, p)
+        # little-endian mixed radix
+        k, q = [], p
+        for d in deg:
+            k.append(q % d)
+            q //= d
+        ref = np.exp(2j * np.pi * np.array(k) / deg)
+        assert np.max(np.abs(_cx(x) - ref)) <= 1e-15
+        for i, d in enumerate(deg):
+            re, im = frc(x[i])
+            z = (re, im)
+            # z^d exactly in rationals
+            pr, pi_ = Fraction(1), Fraction(0)
+            for _ in range(int(d)):
+                pr, pi_ = pr * z[0] - pi_ * z[1], pr * z[1] + pi_ * z[0]
+            assert abs(pr - 1) <= 8 * Fraction(U[L]) and abs(pi_) <= 8 * Fraction(U[L])
+            if d == 2:
+                assert pi_ == 0 and pr == 1   # +-1 exactly
+        seen.add(tuple(np.round(_cx(x), 12)))
+    assert len(seen) == B
+
+
+@pytest.mark.parametrize("L", [1, 2])
+def test_f_equals_g_paths_stay_put(L):
+    n = 3
+    deg = [2, 3, 2]
+    s = synth.system_from_terms(n, [[(1, {i: deg[i]}), (-1, {})] for i in range(n)])
+    gamma = complex(np.cos(1.1), np.sin(1.1))
+    r = oracle.track(s, gamma, range(12), oracle.Opts(prec=L))
+    assert np.all(r["status"] == 1)
+    for p in range(12):
+        x0 = oracle.start_solution(L, np.array(deg, dtype=np.int32), p)
+        assert np.max(np.abs(_cx(r["x"][p]) - _cx(x0))) <= 1e-14
+
+
+def _branch_endpoint(gamma, c, d, x0, steps=20000):
+    t = np.linspace(0.0, 1.0, steps + 1)
+    w = (gamma * (1 - t) + t * c) / (gamma * (1 - t) + t)
+    ang = np.unwrap(np.angle(w))
+    ang += (np.angle(x0 ** d) - ang[0])            # w(0) = 1 = x0^d
+    theta0 = np.angle(x0)
+    # x(t) = |w|^(1/d) exp(i (theta0 + (ang - ang0)/d))
+    return np.abs(w[-1]) ** (1.0 / d) * np.exp(1j * (theta0 + (ang[-1] - ang[0]) / d))
+
+
+@pytest.mark.parametrize("L", [1, 2])
+def test_decoupled_closed_form(L):
+    rng = np.random.default_rng(7)
+    n = 3
+    deg = np.array([3, 2, 3], dtype=np.int32)
+    cs = [0.5 * synth.unit_complex(rng) * (1 + rng.uniform()) for _ in range(n)]
+    s = synth.system_from_terms(n, [[(1, {i: int(deg[i])}), (-cs[i], {})] for i in range(n)])
+    gamma = synth.unit_complex(rng)
+    B = int(np.prod(deg))
+    r = oracle.track(s, gamma, range(B), oracle.Opts(prec=L))
+    assert np.all(r["status"] == 1)
+    for p in range(B):
+        x0 = _cx(oracle.start_solution(1, deg, p))
+        for i in range(n):
+            ref = _branch_endpoint(gamma, cs[i], int(deg[i]), x0[i])
+            assert abs(_cx(r["x"][p])[i] - ref) <= 1e-9, (p, i)
+
+
+def test_univariate_against_numpy_roots():
+    rng = np.random.default_rng(11)
+    d = 6
+    coeffs = [synth.unit_complex(rng) for _ in range(d + 1)]  # x^d ... x^0
+    s = synth.system_from_terms(1, [[(coeffs[d - e], {0: e} if e else {}) for e in range(d + 1)]])
+    gamma = synth.unit_complex(rng)
+    r = oracle.track(s, gamma, range(d), oracle.Opts(prec=2))
+    assert np.all(r["status"] == 1)
+    got = np.sort_complex(_cx(r["x"][:, 0]))
+    ref = np.roots(coeffs)
+    for z in got:
+        assert np.min(np.abs(ref - z)) <= 1e-12
+    for z in ref:
+        assert np.min(np.abs(got - z)) <= 1e-12
+
+
+def _residual_ok(s, r, L, c=256.0):
+    X = r["x"]
+    val, _, sv, _ = oracle.eval_homotopy(s, L, X, None, jac=False)
+    res = np.abs(val.sum(-1)).max(-1)   # [p, i]
+    return np.all(res <= c * U[L] * np.maximum(sv, 1.0))
+
+
+@pytest.mark.parametrize("L", [1, 2])
+def test_bezout_count_small(L):
+    s = synth.tracking_small()
+    r = oracle.track(s, synth.gamma_of(s), range(8), oracle.Opts(prec=L))
+    assert np.all(r["status"] == 1)
+    E = _cx(r["x"])
+    for a in range(8):
+        for b in range(a + 1, 8):
+            assert np.max(np.abs(E[a] - E[b])) > 1e-6
+    assert _residual_ok(s, r, L)
+
+
+def test_bezout_count_cubic_n3():
+    """n = 3, degree 3 per equation (x_i^3, 1, 6 random others): 27 distinct endpoints."""
+    rng = np.random.default_rng(12)
+    eqs = [synth._equation_with_anchor(rng, [0, 1, 2], i, 3, 8) for i in range(3)]
+    s = synth.system_from_terms(3, eqs)
+    r = oracle.track(s, synth.unit_complex(rng), range(27), oracle.Opts(prec=1))
+    assert np.all(r["status"] == 1)
+    E = _cx(r["x"])
+    d = np.abs(E[:, None, :] - E[None, :, :]).max(-1) + np.eye(27)
+    assert d.min() > 1e-6
+    assert _residual_ok(s, r, 1)
+
+
+def test_mixed_and_plain_agree_double_double():
+    s = synth.tracking_small()
+    g = synth.gamma_of(s)
+    plain = oracle.track(s, g, range(8), oracle.Opts(prec=2, mixed=0))
+    mixed = oracle.track(s, g, range(8), oracle.Opts(prec=2, mixed=1))
+    assert np.all(plain["status"] == 1) and np.all(mixed["status"] == 1)
+    from tests.exact import limb_sum_diff
+    d = np.abs(limb_sum_diff(plain["x"], mixed["x"])).max()
+    assert d <= 1e-24 * max(1.0, np.abs(_cx(plain["x"])).max())
+    assert _residual_ok(s, mixed, 2)
+
+
+def test_forced_divergence_exactly_one():
+    # f = 0 x^2 + x - 1 keeps degree 2 (start x^2 - 1) but has one finite root
+    s = synth.system_from_terms(1, [[(0.0, {0: 2}), (1.0, {0: 1}), (-1.0, {})]])
+    gamma = complex(np.cos(0.7), np.sin(0.7))
+    r = oracle.track(s, gamma, range(2), oracle.Opts(prec=1))
+    reasons = sorted(oracle.REASONS[int(v)] for v in r["reason"])
+    assert reasons == ["DIVERGED", "SUCCESS"]
+    ok = int(np.argmax(r["status"] == 1))
+    assert abs(_cx(r["x"][ok, 0]) - 1.0) <= 1e-12
+
+
+def test_forced_failures():
+    s = synth.tracking_small()
+    g = synth.gamma_of(s)
+    deg = oracle.degrees(s)
+    x0 = oracle.start_solution(1, deg, 0)
+    xn = x0.copy()
+    xn[1, 0, 0] = np.nan
+    assert oracle.REASONS[oracle.track_path(s, g, xn, oracle.Opts())["reason"]] == "NAN"
+    r = oracle.track_path(s, g, x0, oracle.Opts(h_min=0.1, h_init=0.01))
+    assert oracle.REASONS[r["reason"]] == "STEP_UNDERFLOW" and r["status"] == -1
+    r = oracle.track_path(s, g, x0, oracle.Opts(max_steps=1))
+    assert oracle.REASONS[r["reason"]] == "MAX_STEPS" and r["status"] == -1
+    # at x = 0 both g and f = x_i^2 - 1 have a zero Jacobian: every solve is singular
+    f = synth.system_from_terms(2, [[(1, {0: 2}), (-1, {})], [(1, {1: 2}), (-1, {})]])
+    r = oracle.track_path(f, g, np.zeros((2, 2, 1)), oracle.Opts())
+    assert oracle.REASONS[r["reason"]] == "SINGULAR" and r["status"] == -1
