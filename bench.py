@@ -1,0 +1,180 @@
+"""Benchmark of the hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec 1|2|4]
+
+A step is one ph_eval_jac launch over the evaluation workload: n = 32
+equations and unknowns, 64 terms per equation over k = 8 distinct variables
+with exponents 1..3, unit-modulus coefficients, 65536 points on the unit torus
+with t ~ U[0,1) -- values and full Jacobian of gamma(1-t) g + t f.  Inputs are
+resident in HBM before timing starts; the K launches are bracketed by HIP
+events on the launch stream.  Prints ONE JSON line.
+
+The roofline object uses algorithmic FP64 flops per point from the cost model
+(per term: 3k-3+#{a>=2} complex products, k+1 complex additions, #{a>=2}+1
+real scalings; flops per complex operation 6/2/2 in double, 80/40/16 in
+double double, 660/212/124 in quad double as executed by the device
+arithmetic) and compulsory bytes per point (x, t, H, J).  cpu_baseline is the
+oracle (plain C, expansion arithmetic, symbolic derivatives) on a bounded
+sample of the same points, on the host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64 = 78.6e12      # MI355X vector FP64 (FMA = 2 flops)
+PEAK_HBM = 8.0e12        # bytes/s
+CMUL = {1: 6, 2: 80, 4: 660}
+CADD = {1: 2, 2: 40, 4: 212}
+CSCALE = {1: 2, 2: 16, 4: 124}
+PREC_NAME = {1: "complex double", 2: "complex double double", 4: "complex quad double"}
+
+
+def flops_per_point(sysm, L):
+    """Algorithmic FP64 flops of H and J at one point (cost model above),
+    including the total-degree start terms x_i^{d_i} and -1."""
+    fl = 0
+    deg = sysm.degrees()
+    terms = []
+    for s in range(sysm.n_terms):
+        a, b = sysm.term_fac_off[s], sysm.term_fac_off[s + 1]
+        terms.append(list(sysm.fac_exp[a:b]))
+    terms += [[int(d)] for d in deg] + [[] for _ in deg]
+    for ex in terms:
+        k = len(ex)
+        n2 = sum(1 for e in ex if e >= 2)
+        if k == 0:
+            fl += CADD[L] + CSCALE[L]
+            continue
+        prods = 3 * k - 3 + n2
+        fl += prods * CMUL[L] + (k + 1) * CADD[L] + (n2 + 1) * CSCALE[L]
+    return fl
+
+
+def bytes_per_point(sysm, L):
+    n, m = sysm.n_var, sysm.n_eq
+    return 16 * L * (n + m + m * n) + 8
+
+
+def cpu_baseline(sysm, L, x, t, gamma, target_s=15.0):
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    # calibrate on one point, then size the sample for ~target_s of CPU work
+    t0 = time.perf_counter()
+    oracle.eval_homotopy(sysm, L, x[:1], t[:1], gamma, scales=False)
+    one = time.perf_counter() - t0
+    npts = int(max(threads, min(len(t), target_s / max(one, 1e-6))))
+    npts = (npts // threads) * threads or threads
+    t0 = time.perf_counter()
+    oracle.eval_threaded(sysm, L, x[:npts], t[:npts], gamma, threads=threads)
+    wall = time.perf_counter() - t0
+    return {"value": npts / wall, "unit": "points/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {npts} of the 65536 points, {PREC_NAME[L]}, {threads} host threads "
+                      f"over contiguous point ranges, {wall:.1f} s wall"}
+
+
+def time_eval(ph, torch, S, sysm, L, npts, steps, warmup, gamma):
+    from paper_1505_00383_amd import synth
+    x, t = synth.torus_points(sysm, npts, L)
+    xs = ph.to_soa(x)
+    tt = torch.as_tensor(t, dtype=torch.float64).cuda()
+    val = torch.empty((sysm.n_eq * 2 * L, npts), dtype=torch.float64, device="cuda")
+    jac = torch.empty((sysm.n_eq * sysm.n_var * 2 * L, npts), dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        ph.eval_jac(S, xs, npts, L, tt, gamma, val=val, jac=jac)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(steps):
+        ph.eval_jac(S, xs, npts, L, tt, gamma, val=val, jac=jac)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    ok = bool(torch.isfinite(val).all()) and bool(torch.isfinite(jac).all())
+    return ms, ok, x, t
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", type=int, default=1, choices=[1, 2, 4])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: the many-path hot path shards paths across GPUs "
+              f"with no exchange until a final gather, and multi-GPU runs are not part of this "
+              f"build (asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1505_00383_amd as ph
+    from paper_1505_00383_amd import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    L = args.prec
+    sysm = synth.eval_dense()
+    gamma = synth.gamma_of(sysm)
+    npts = 65536
+    S = ph.System(sysm)
+    ms, ok, x, t = time_eval(ph, torch, S, sysm, L, npts, args.steps, args.warmup, gamma)
+    fpp = flops_per_point(sysm, L)
+    bpp = bytes_per_point(sysm, L)
+    secs = ms * 1e-3
+    achieved = fpp * npts / secs
+    result = {
+        "metric": "eval+Jacobian points/sec (paths/sec to t=1 in extras), per precision",
+        "value": npts / secs,
+        "unit": "points/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"eval+jacobian of gamma(1-t)g+t f, n=32, 64 terms/eq over k=8 "
+                               f"vars, exponents 1..3, 65536 torus points, {PREC_NAME[L]}",
+                   "prec_limbs": L, "points": npts, "n": 32, "terms": int(sysm.n_terms),
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
+                     "kernel": f"eval_kernel<{L},8,true,true>",
+                     "flops_per_point": fpp, "bytes_per_point": bpp,
+                     "hbm_GBps_compulsory": bpp * npts / secs / 1e9,
+                     "hbm_frac_compulsory": bpp * npts / secs / PEAK_HBM},
+        "finite": ok,
+    }
+    if not args.no_extras:
+        extras = {}
+        for L2 in (1, 2, 4):
+            if L2 == L:
+                continue
+            ms2, ok2, _, _ = time_eval(ph, torch, S, sysm, L2, npts, max(3, args.steps // 4), 1, gamma)
+            f2 = flops_per_point(sysm, L2)
+            extras[f"eval_prec{L2}"] = {"points_per_s": npts / (ms2 * 1e-3), "ms": ms2,
+                                        "fp64_frac": f2 * npts / (ms2 * 1e-3) / PEAK_FP64,
+                                        "finite": ok2}
+        result["extras"] = extras
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(sysm, L, x, t, gamma)
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

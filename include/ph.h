@@ -1,0 +1,173 @@
+/*
+ * ph.h -- C ABI of the many-path polynomial homotopy library for AMD MI355X
+ * (gfx950).  Hot path of J. Verschelde and X. Yu, "Tracking Many Solution
+ * Paths of a Polynomial Homotopy on a Graphics Processing Unit" (2015).
+ *
+ * Conventions shared by every call:
+ *   - Every function returns int: PH_OK (0) or a negative PH_E* code.  The
+ *     message of the last failure on the calling thread is ph_last_error().
+ *   - Precision `prec` is the number of FP64 limbs of every real quantity:
+ *     PH_D = 1 (complex double), PH_DD = 2 (double double), PH_QD = 4 (quad
+ *     double), as in Section 1 of the paper.  Limbs are non-overlapping with
+ *     the largest first; a value is the exact sum of its limbs.
+ *   - Point data is structure-of-arrays with the point (path) index fastest,
+ *     the "vertical" layout of the paper (Section 3, Table 5): element
+ *     (point p, row r) lives at base[r * ld + p], ld >= number of points.
+ *       x   : row r = (var * 2 + c) * L + l          c = 0 real, 1 imaginary
+ *       val : row r = (eq * 2 + c) * L + l
+ *       jac : row r = ((eq * n_var + var) * 2 + c) * L + l
+ *   - Pointers marked "device" are device memory on the current HIP device;
+ *     the caller owns them.  `stream` is a hipStream_t (NULL: default stream).
+ *   - A numerical failure of one path is not an error: it is reported through
+ *     the per-path status (1 success, -1 failure; 0 is used internally for
+ *     "continue", Section 2) and a reason code.
+ */
+#ifndef PH_H
+#define PH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PH_OK 0
+#define PH_EINVAL (-1)       /* bad size, pointer, precision or exponent */
+#define PH_ENOMEM (-2)       /* device or host allocation failed */
+#define PH_EHIP (-3)         /* a HIP runtime call failed (message has the HIP error) */
+#define PH_EUNSUPPORTED (-4) /* valid request outside what this build handles */
+
+#define PH_D 1
+#define PH_DD 2
+#define PH_QD 4
+
+/* Per-path reasons (status -1 unless PH_R_SUCCESS). */
+#define PH_R_NONE 0
+#define PH_R_SUCCESS 1
+#define PH_R_DIVERGED 2       /* ||x||_inf exceeded diverge_norm */
+#define PH_R_STEP_UNDERFLOW 3 /* step size fell below h_min */
+#define PH_R_MAX_STEPS 4      /* step budget exhausted */
+#define PH_R_SINGULAR 5       /* last rejected step had a rank-deficient Jacobian */
+#define PH_R_NAN 6            /* NaN or Inf in the path state */
+
+typedef struct ph_system ph_system; /* opaque; immutable after creation */
+
+/*
+ * ph_system_create -- compile a sparse polynomial system into device term
+ * tables (the paper's "instructions", idx and cff, Table 8).
+ *   n_eq, n_var    : 1 <= n_var <= n_eq <= 64 (least squares allowed for eval)
+ *   eq_term_off    : host, n_eq + 1 offsets; terms of equation i are
+ *                    eq_term_off[i] .. eq_term_off[i+1]-1
+ *   term_fac_off   : host, n_terms + 1 offsets into fac_var / fac_exp; a term
+ *                    with no factor is a constant
+ *   fac_var        : host, variable index of each factor, strictly increasing
+ *                    inside a term
+ *   fac_exp        : host, exponent of each factor, 1 <= e <= 64
+ *   coef           : host, [n_terms][2][coef_limbs] complex coefficients
+ *   coef_limbs     : 1, 2 or 4
+ *   out            : receives the handle
+ * Each term is c * prod x_j^{a_j}, decomposed as in Section 1: the product of
+ * the variables that occur, times the factor c * prod x_j^{a_j - 1} common to
+ * all derivatives.  At most 32 factors per term.  All host arrays are copied;
+ * the call synchronises the device.  Errors: PH_EINVAL on malformed input,
+ * PH_EUNSUPPORTED for n > 64 or k > 32, PH_ENOMEM / PH_EHIP.
+ */
+int ph_system_create(int32_t n_eq, int32_t n_var, const int32_t *eq_term_off,
+                     const int32_t *term_fac_off, const int32_t *fac_var,
+                     const int32_t *fac_exp, const double *coef, int32_t coef_limbs,
+                     ph_system **out);
+
+/* Free the handle and its device tables (synchronises the device). */
+int ph_system_destroy(ph_system *s);
+
+/* Shape of a system: any output pointer may be NULL. */
+int ph_system_info(const ph_system *s, int32_t *n_eq, int32_t *n_var, int64_t *n_terms,
+                   int32_t *max_factors);
+
+/* deg[i] = total degree of equation i (host array of n_eq). */
+int ph_system_degrees(const ph_system *s, int32_t *deg);
+
+/*
+ * ph_start_solutions -- start points of the total-degree start system
+ * g_i = x_i^{d_i} - 1 (the start system of Eq. (1) used by ph_track):
+ * path p maps to the multi-index (k_0 .. k_{n-1}) by little-endian mixed
+ * radix p = sum_i k_i prod_{l<i} d_l and x_i = exp(2 pi i k_i / d_i).
+ * Writes paths first_path .. first_path+npaths-1 into the device SoA array x
+ * (row = (var*2+c)*prec + l, leading dimension ld).  Degrees must divide 12
+ * (1, 2, 3, 4, 6): PH_EUNSUPPORTED otherwise.  Asynchronous on stream.
+ */
+int ph_start_solutions(const ph_system *target, int32_t prec, int64_t first_path,
+                       int64_t npaths, double *x, int64_t ld, void *stream);
+
+/*
+ * ph_eval_jac -- values and Jacobian of the homotopy of Eq. (1),
+ *   H(x, t) = gamma (1 - t) g(x) + t f(x),   J = dH/dx,
+ * at npts points, by reverse-mode differentiation of every term's variable
+ * product (Section 3, Table 6), the coefficient c(t) folded per point.
+ *   target : f;  start : g, or NULL for g_i = x_i^{d_i} - 1 with d_i = deg f_i
+ *   gamma  : host, {re, im} FP64
+ *   prec   : PH_D, PH_DD or PH_QD
+ *   t      : device, npts FP64 values of t, or NULL for t = 1 (f alone)
+ *   x      : device SoA, rows (var*2+c)*prec+l, leading dimension ld
+ *   val    : device SoA output, rows (eq*2+c)*prec+l
+ *   jac    : device SoA output, rows ((eq*n_var+var)*2+c)*prec+l, or NULL
+ * npts = 0 is a no-op.  No allocation; asynchronous on stream.  NaN/Inf
+ * inputs propagate unchecked.  Errors: PH_EINVAL (null pointers, ld < npts,
+ * start shape differs from target), PH_EHIP (launch failure).
+ */
+int ph_eval_jac(const ph_system *target, const ph_system *start, const double gamma[2],
+                int32_t prec, int64_t npts, const double *t, const double *x, int64_t ld,
+                double *val, double *jac, void *stream);
+
+/*
+ * Options of the path tracker (Section 2; the paper gives no constants,
+ * defaults from ph_track_opts_default):
+ *   prec            residual precision PH_D / PH_DD / PH_QD
+ *   mixed           1: Newton update solved in complex FP64 from the rounded
+ *                   Jacobian and residual, added to the prec-limb point
+ *                   (refinement); 0: every step in prec limbs
+ *   predictor_order 1 (secant; zero order on the first step)
+ *   max_newton      corrector steps per predictor step (3)
+ *   expand_after    successes before the step grows (3)
+ *   polish_max      Newton steps of the polish at t = 1 (8)
+ *   h_init, h_min, h_max   initial / smallest / largest step (0.01, 1e-10, 0.1)
+ *   shrink, expand  step factors after rejection / expansion (0.5, 1.5)
+ *   tol_dx          corrector converged when ||dx|| <= tol_dx max(1,||x||) (1e-8)
+ *   diverge_norm    ||x||_inf beyond this fails the path (1e8)
+ *   polish_tol      polish target relative to max(1,||x||); < 0 selects 8 u_prec
+ *   max_steps       predictor steps per path (100000)
+ */
+typedef struct {
+    int32_t prec, mixed, predictor_order, max_newton, expand_after, polish_max;
+    double h_init, h_min, h_max, shrink, expand, tol_dx, diverge_norm, polish_tol;
+    int64_t max_steps;
+} ph_track_opts;
+
+/* Counts filled by ph_track when a report pointer is given. */
+typedef struct {
+    int64_t n_success, n_fail, n_diverged, n_step_underflow, n_max_steps, n_singular, n_nan;
+    int64_t steps, rejected, newton_its;
+    double seconds;
+} ph_track_report;
+
+/* Fill *o with the defaults listed above (prec = PH_D, mixed = 0). */
+int ph_track_opts_default(ph_track_opts *o);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *ph_last_error(void);
+
+/*
+ * ph_arith_probe -- apply one device arithmetic operation elementwise, for
+ * checking the double double / quad double building blocks against exact
+ * results.  op 0 add, 1 sub, 2 mul on reals [n][prec]; op 3 add, 4 multiply
+ * on complexes [n][2][prec]; op 5 complex a times the real double b[i][0][0].
+ * a, b, out: device arrays.  Asynchronous on stream.  PH_EINVAL on bad op/prec.
+ */
+int ph_arith_probe(int32_t prec, int32_t op, int64_t n, const double *a, const double *b,
+                   double *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PH_H */

@@ -1,0 +1,198 @@
+"""Python binding of libph (many-path polynomial homotopy hot path on MI355X).
+
+Argument marshalling only: every step of evaluation and tracking runs in the
+HIP kernels of ``libph.so``; torch provides device memory and streams.  The
+library is loaded lazily and any call fails loudly (``PHError``) when it is
+missing or no GPU is present -- there is no CPU fallback.
+
+Layouts (see include/ph.h): point data is structure-of-arrays with the point
+index fastest.  ``to_soa`` / ``from_soa`` convert between the natural
+[npts, n, 2, L] array and the [n*2*L, ld] device matrix.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libph.so")
+
+PH_D, PH_DD, PH_QD = 1, 2, 4
+REASONS = {0: "NONE", 1: "SUCCESS", 2: "DIVERGED", 3: "STEP_UNDERFLOW", 4: "MAX_STEPS",
+           5: "SINGULAR", 6: "NAN"}
+EXPORTED = ["ph_system_create", "ph_system_destroy", "ph_system_info", "ph_system_degrees",
+            "ph_start_solutions", "ph_eval_jac", "ph_track_opts_default", "ph_last_error",
+            "ph_arith_probe"]
+
+
+class PHError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libph.so (no GPU needed for loading).  Raises PHError if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise PHError(f"{path} is missing: build it with `python -m paper_1505_00383_amd.build`")
+    L = ctypes.CDLL(path)
+    P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.ph_system_create.argtypes = [i32, i32, P, P, P, P, P, i32, ctypes.POINTER(P)]
+    L.ph_system_destroy.argtypes = [P]
+    L.ph_system_info.argtypes = [P, P, P, P, P]
+    L.ph_system_degrees.argtypes = [P, P]
+    L.ph_start_solutions.argtypes = [P, i32, i64, i64, P, i64, P]
+    L.ph_eval_jac.argtypes = [P, P, P, i32, i64, P, P, i64, P, P, P]
+    L.ph_track_opts_default.argtypes = [P]
+    L.ph_last_error.restype = ctypes.c_char_p
+    L.ph_arith_probe.argtypes = [i32, i32, i64, P, P, P, P]
+    for name in EXPORTED:
+        fn = getattr(L, name)
+        if name != "ph_last_error":
+            fn.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise PHError(f"libph error {rc}: {load_library().ph_last_error().decode()}")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise PHError("no HIP device available: libph runs on the GPU only")
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# layout marshalling
+# ---------------------------------------------------------------------------
+def to_soa(x, ld: int | None = None, device="cuda"):
+    """[npts, n, 2, L] (numpy or torch) -> device tensor [n*2*L, ld], point fastest."""
+    torch = _torch()
+    xt = torch.as_tensor(np.ascontiguousarray(x) if isinstance(x, np.ndarray) else x,
+                         dtype=torch.float64)
+    npts = xt.shape[0]
+    ld = ld or npts
+    rows = xt[0].numel() if npts else int(np.prod(xt.shape[1:]))
+    out = torch.zeros((rows, ld), dtype=torch.float64, device=device)
+    if npts:
+        out[:, :npts] = xt.reshape(npts, rows).to(device).T
+    return out
+
+
+def from_soa(m, npts: int, shape_tail):
+    """device tensor [rows, ld] -> numpy [npts, *shape_tail]."""
+    return m[:, :npts].T.contiguous().cpu().numpy().reshape((npts,) + tuple(shape_tail))
+
+
+# ---------------------------------------------------------------------------
+# systems
+# ---------------------------------------------------------------------------
+class System:
+    """Device term tables of a polynomial system (ph_system_create)."""
+
+    def __init__(self, sysm, coef_limbs: int = 1):
+        lib = load_library()
+        self.n_eq, self.n_var = int(sysm.n_eq), int(sysm.n_var)
+        eq = np.ascontiguousarray(sysm.eq_term_off, dtype=np.int32)
+        tf = np.ascontiguousarray(sysm.term_fac_off, dtype=np.int32)
+        fv = np.ascontiguousarray(sysm.fac_var, dtype=np.int32)
+        fe = np.ascontiguousarray(sysm.fac_exp, dtype=np.int32)
+        cf = np.ascontiguousarray(sysm.coef, dtype=np.float64)
+        if coef_limbs != 1:
+            cf = np.ascontiguousarray(cf.reshape(-1, 2, coef_limbs))
+        h = ctypes.c_void_p()
+        _check(lib.ph_system_create(self.n_eq, self.n_var, eq.ctypes.data, tf.ctypes.data,
+                                    fv.ctypes.data if fv.size else None,
+                                    fe.ctypes.data if fe.size else None, cf.ctypes.data,
+                                    coef_limbs, ctypes.byref(h)))
+        self._h = h
+        self.source = sysm
+
+    @property
+    def handle(self):
+        return self._h
+
+    def degrees(self) -> np.ndarray:
+        d = np.zeros(self.n_eq, dtype=np.int32)
+        _check(load_library().ph_system_degrees(self._h, d.ctypes.data))
+        return d
+
+    def info(self):
+        ne, nv, mk = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        nt = ctypes.c_int64()
+        _check(load_library().ph_system_info(self._h, ctypes.byref(ne), ctypes.byref(nv), ctypes.byref(nt),
+                                   ctypes.byref(mk)))
+        return dict(n_eq=ne.value, n_var=nv.value, n_terms=nt.value, max_factors=mk.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().ph_system_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def eval_jac(sys: System, x_soa, npts: int, prec: int, t=None, gamma=1.0 + 0j, start=None,
+             val=None, jac=None, want_jac: bool = True, stream=None):
+    """H(x,t) = gamma(1-t) g + t f and dH/dx at npts points (ph_eval_jac).
+
+    x_soa: device [n_var*2*prec, ld]; t: device [npts] or None (t = 1).
+    Returns (val [n_eq*2*prec, ld], jac [n_eq*n_var*2*prec, ld] or None)."""
+    torch = _torch()
+    ld = x_soa.shape[1]
+    if val is None:
+        val = torch.empty((sys.n_eq * 2 * prec, ld), dtype=torch.float64, device=x_soa.device)
+    if want_jac and jac is None:
+        jac = torch.empty((sys.n_eq * sys.n_var * 2 * prec, ld), dtype=torch.float64,
+                          device=x_soa.device)
+    g = (ctypes.c_double * 2)(complex(gamma).real, complex(gamma).imag)
+    _check(load_library().ph_eval_jac(sys.handle, None if start is None else start.handle, g, prec, npts,
+                            _ptr(t), _ptr(x_soa), ld, _ptr(val), _ptr(jac) if want_jac else None,
+                            _stream(stream)))
+    return val, (jac if want_jac else None)
+
+
+def start_solutions(sys: System, prec: int, first: int, npaths: int, out=None, stream=None):
+    """Roots-of-unity start points (ph_start_solutions) -> device [n*2*prec, npaths]."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((sys.n_var * 2 * prec, max(npaths, 1)), dtype=torch.float64,
+                          device="cuda")
+    _check(load_library().ph_start_solutions(sys.handle, prec, first, npaths, _ptr(out), out.shape[1],
+                                   _stream(stream)))
+    return out
+
+
+def arith_probe(prec: int, op: int, a, b, stream=None):
+    """Device arithmetic on [n, prec] reals (op 0..2) or [n, 2, prec] complexes (op 3..5)."""
+    torch = _torch()
+    at = torch.as_tensor(a, dtype=torch.float64).contiguous().cuda()
+    bt = torch.as_tensor(b, dtype=torch.float64).contiguous().cuda()
+    out = torch.empty_like(at)
+    _check(load_library().ph_arith_probe(prec, op, at.shape[0], _ptr(at), _ptr(bt), _ptr(out),
+                               _stream(stream)))
+    return out.cpu().numpy()

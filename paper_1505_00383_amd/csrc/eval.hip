@@ -1,0 +1,312 @@
+// eval.hip -- values and Jacobian of gamma (1-t) g(x) + t f(x) at many points
+// (Eq. (1) of the paper), the evaluation stage of Section 2 and the kernels of
+// Section 3 (coefficients c(t), monomials by reverse mode, sums) fused into one.
+//
+// Mapping onto gfx950:
+//   * one lane = one point; a wave runs the merged term stream of one
+//     equation on 64 points at once, so every term index, exponent and
+//     coefficient is wave-uniform and comes through scalar loads (Section 3:
+//     all threads of a block evaluate the same monomial at different points);
+//   * all waves of a workgroup work on the same 64 points, each on its own
+//     equations, and share the coordinates staged once in LDS in the layout
+//     [row][lane] (row = (var*2+c)*L + l), which is conflict-free for a wave;
+//   * point data in HBM is structure-of-arrays with the point index fastest
+//     (the transposed layout of Table 5), so every global access of a wave is
+//     one contiguous 512-byte segment;
+//   * the Jacobian row of the equation in flight is accumulated in place in
+//     the output array (L2-resident during the equation); the first
+//     contribution to a column is a store, columns no term touches get a zero.
+//
+// Per term c * prod_l x_{j_l}^{a_l} (Section 1 decomposition, Table 6):
+//   cf   = c(t) * prod_l x_{j_l}^{a_l - 1}         common factor
+//   q_l  = cf * x_{j_1} ... x_{j_{l-1}}           forward products
+//   value = q_k * x_{j_k}
+//   d/dx_{j_l} = a_l * q_l * (x_{j_{l+1}} ... x_{j_k})   backward products
+// which is 3k - 3 products including the two that fold cf in (3k - 5 for the
+// bare variable product, as counted in Table 6).
+#include <hip/hip_runtime.h>
+
+#include "ph_arith.hpp"
+#include "ph_internal.hpp"
+
+namespace ph {
+
+struct EvalArgs {
+    const int32_t *eq_off;
+    const int4 *tdesc;
+    const uint32_t *fac;
+    const double *coef;
+    const int32_t *zc_off;
+    const int32_t *zc;
+    const double *t;
+    const double *x;
+    double *val;
+    double *jac;
+    int64_t npts, ld;
+    double gre, gim;
+    int n_eq, n_var, eq_stride;
+};
+
+template <int L>
+__device__ __forceinline__ C<L> load_x(const double *__restrict__ xl, int var, int lane)
+{
+    C<L> z;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        z.re.v[l] = xl[((var * 2 + 0) * L + l) * 64 + lane];
+        z.im.v[l] = xl[((var * 2 + 1) * L + l) * 64 + lane];
+    }
+    return z;
+}
+
+template <int L>
+__device__ __forceinline__ C<L> load_x_global(const double *__restrict__ x, int var, int64_t ld,
+                                              int64_t p)
+{
+    C<L> z;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        z.re.v[l] = x[((int64_t)(var * 2 + 0) * L + l) * ld + p];
+        z.im.v[l] = x[((int64_t)(var * 2 + 1) * L + l) * ld + p];
+    }
+    return z;
+}
+
+// Add (or store, on the first touch) one partial derivative into the output.
+template <int L>
+__device__ __forceinline__ void jac_acc(double *__restrict__ jrow, int64_t ld, bool first, C<L> d,
+                                        bool act)
+{
+    if (!act) return;
+    if (first) {
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            jrow[(int64_t)l * ld] = d.re.v[l];
+            jrow[(int64_t)(L + l) * ld] = d.im.v[l];
+        }
+    } else {
+        C<L> o;
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            o.re.v[l] = jrow[(int64_t)l * ld];
+            o.im.v[l] = jrow[(int64_t)(L + l) * ld];
+        }
+        o = c_add<L>(o, d);
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            jrow[(int64_t)l * ld] = o.re.v[l];
+            jrow[(int64_t)(L + l) * ld] = o.im.v[l];
+        }
+    }
+}
+
+template <int L, int KMAX, bool XLDS, bool JAC>
+__global__ void __launch_bounds__(512) eval_kernel(EvalArgs a)
+{
+    extern __shared__ double xl[];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int W = blockDim.x >> 6;
+    const int64_t p = (int64_t)blockIdx.x * 64 + lane;
+    const bool act = p < a.npts;
+    const int nv = a.n_var;
+
+    if constexpr (XLDS) {
+        const int rows = nv * 2 * L;
+        for (int r = w; r < rows; r += W) xl[r * 64 + lane] = act ? a.x[(int64_t)r * a.ld + p] : 0.0;
+        __syncthreads();
+    }
+    auto X = [&](int var) -> C<L> {
+        if constexpr (XLDS)
+            return load_x<L>(xl, var, lane);
+        else
+            return act ? load_x_global<L>(a.x, var, a.ld, p) : c_zero<L>();
+    };
+
+    // c(t) per point: t for target terms, gamma (1 - t) for start terms;
+    // (1 - t) is exact in two limbs.
+    double tv = 1.0;
+    if (a.t) tv = act ? a.t[p] : 0.0;
+    C<L> gs = c_zero<L>();
+    if (a.t) {
+        double o, oe;
+        two_sum(1.0, -tv, o, oe);
+        R<L> omt = r_zero<L>();
+        omt.v[0] = o;
+        if constexpr (L > 1) omt.v[1] = oe;
+        gs = c_mul_r<L>(c_from<L>(a.gre, a.gim), omt);
+    }
+
+    for (int i = blockIdx.y * W + w; i < a.n_eq; i += a.eq_stride) {
+        C<L> v = c_zero<L>();
+        double *jrow0 = JAC ? a.jac + (int64_t)i * nv * 2 * L * a.ld + p : nullptr;
+        const int s0 = a.eq_off[i], s1 = a.eq_off[i + 1];
+        for (int s = s0; s < s1; ++s) {
+            const int4 d = a.tdesc[s];
+            const int k = d.x;
+            C<L> c;
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                c.re.v[l] = a.coef[(int64_t)s * 8 + l];
+                c.im.v[l] = a.coef[(int64_t)s * 8 + 4 + l];
+            }
+            c = d.z ? c_mul<L>(c, gs) : c_mul_d<L>(c, tv);
+            if (k == 0) {
+                v = c_add<L>(v, c);
+                continue;
+            }
+            uint32_t fw[KMAX];
+            C<L> xv[KMAX];
+            C<L> q[KMAX];
+#pragma unroll
+            for (int l = 0; l < KMAX; ++l)
+                if (l < k) fw[l] = a.fac[d.y + l];
+            // common factor c(t) * prod x^(a-1)
+            C<L> cf = c;
+#pragma unroll
+            for (int l = 0; l < KMAX; ++l) {
+                if (l < k) {
+                    xv[l] = X(fac_var(fw[l]));
+                    const int e = fac_exp(fw[l]);
+                    for (int r = 1; r < e; ++r) cf = c_mul<L>(cf, xv[l]);
+                }
+            }
+            // forward products
+            q[0] = cf;
+#pragma unroll
+            for (int l = 1; l < KMAX; ++l)
+                if (l < k) q[l] = c_mul<L>(q[l - 1], xv[l - 1]);
+            C<L> last = q[0], xlast = xv[0];
+#pragma unroll
+            for (int l = 1; l < KMAX; ++l)
+                if (l == k - 1) {
+                    last = q[l];
+                    xlast = xv[l];
+                }
+            v = c_add<L>(v, c_mul<L>(last, xlast));
+            if constexpr (JAC) {
+                // backward products: partial_l = a_l * q_l * (x_{l+1} ... x_{k-1})
+                C<L> sfx = xlast;
+#pragma unroll
+                for (int l = KMAX - 1; l >= 0; --l) {
+                    if (l < k) {
+                        C<L> part = (l == k - 1) ? q[l] : c_mul<L>(q[l], sfx);
+                        if (l < k - 1 && l > 0) sfx = c_mul<L>(sfx, xv[l]);
+                        const int e = fac_exp(fw[l]);
+                        if (e != 1) part = c_mul_d<L>(part, (double)e);
+                        const int var = fac_var(fw[l]);
+                        jac_acc<L>(jrow0 + (int64_t)var * 2 * L * a.ld, a.ld, (fw[l] & FAC_FIRST) != 0,
+                                   part, act);
+                    }
+                }
+            }
+        }
+        if (act) {
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                a.val[((int64_t)(i * 2 + 0) * L + l) * a.ld + p] = v.re.v[l];
+                a.val[((int64_t)(i * 2 + 1) * L + l) * a.ld + p] = v.im.v[l];
+            }
+            if constexpr (JAC) {
+                for (int z = a.zc_off[i]; z < a.zc_off[i + 1]; ++z) {
+                    double *jr = jrow0 + (int64_t)a.zc[z] * 2 * L * a.ld;
+#pragma unroll
+                    for (int l = 0; l < 2 * L; ++l) jr[(int64_t)l * a.ld] = 0.0;
+                }
+            }
+        }
+    }
+}
+
+template <int L, int KMAX, bool XLDS, bool JAC>
+static int launch4(const EvalArgs &a, int W, int G, size_t lds, hipStream_t st)
+{
+    dim3 grid((unsigned)((a.npts + 63) / 64), (unsigned)G);
+    hipLaunchKernelGGL((eval_kernel<L, KMAX, XLDS, JAC>), grid, dim3(64 * W), XLDS ? lds : 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "eval_kernel launch");
+    return PH_OK;
+}
+
+template <int L, int KMAX>
+static int launch3(const EvalArgs &a, bool xlds, bool jac, int W, int G, size_t lds, hipStream_t st)
+{
+    if (xlds)
+        return jac ? launch4<L, KMAX, true, true>(a, W, G, lds, st)
+                   : launch4<L, KMAX, true, false>(a, W, G, lds, st);
+    return jac ? launch4<L, KMAX, false, true>(a, W, G, lds, st)
+               : launch4<L, KMAX, false, false>(a, W, G, lds, st);
+}
+
+template <int L>
+static int launch2(const EvalArgs &a, int kmax, bool xlds, bool jac, int W, int G, size_t lds,
+                   hipStream_t st)
+{
+    if (kmax <= 4) return launch3<L, 4>(a, xlds, jac, W, G, lds, st);
+    if (kmax <= 8) return launch3<L, 8>(a, xlds, jac, W, G, lds, st);
+    if (kmax <= 16) return launch3<L, 16>(a, xlds, jac, W, G, lds, st);
+    return launch3<L, 32>(a, xlds, jac, W, G, lds, st);
+}
+
+int eval_launch(const DevTable &tab, const double gamma[2], int prec, int64_t npts,
+                const double *t, const double *x, int64_t ld, double *val, double *jac,
+                hipStream_t st)
+{
+    EvalArgs a;
+    a.eq_off = tab.eq_off;
+    a.tdesc = tab.tdesc;
+    a.fac = tab.fac;
+    a.coef = tab.coef;
+    a.zc_off = tab.zc_off;
+    a.zc = tab.zc;
+    a.t = t;
+    a.x = x;
+    a.val = val;
+    a.jac = jac;
+    a.npts = npts;
+    a.ld = ld;
+    a.gre = gamma ? gamma[0] : 1.0;
+    a.gim = gamma ? gamma[1] : 0.0;
+    a.n_eq = tab.n_eq;
+    a.n_var = tab.n_var;
+    // waves per workgroup: each wave takes its own equations of the same 64
+    // points; more equation groups when there are few point blocks
+    const int W = tab.n_eq >= 4 ? 4 : tab.n_eq;
+    const int64_t blocks = (npts + 63) / 64;
+    int G = 1;
+    while (blocks * G < 1024 && G * W * 2 <= tab.n_eq) G *= 2;
+    a.eq_stride = G * W;
+    const size_t lds = (size_t)tab.n_var * 2 * prec * 64 * sizeof(double);
+    const bool xlds = lds <= 160 * 1024;
+    const bool wj = jac != nullptr;
+    switch (prec) {
+    case 1: return launch2<1>(a, tab.kmax, xlds, wj, W, G, lds, st);
+    case 2: return launch2<2>(a, tab.kmax, xlds, wj, W, G, lds, st);
+    default: return launch2<4>(a, tab.kmax, xlds, wj, W, G, lds, st);
+    }
+}
+
+}  // namespace ph
+
+using namespace ph;
+
+extern "C" int ph_eval_jac(const ph_system *target, const ph_system *start, const double gamma[2],
+                           int32_t prec, int64_t npts, const double *t, const double *x, int64_t ld,
+                           double *val, double *jac, void *stream)
+{
+    if (!target) return fail(PH_EINVAL, "null target system");
+    if (prec != 1 && prec != 2 && prec != 4) return fail(PH_EINVAL, "prec must be 1, 2 or 4");
+    if (npts < 0) return fail(PH_EINVAL, "npts < 0");
+    if (npts == 0) return PH_OK;
+    if (!x || !val) return fail(PH_EINVAL, "null x or val");
+    if (ld < npts) return fail(PH_EINVAL, "ld < npts");
+    if (start && (start->h.n_eq != target->h.n_eq || start->h.n_var != target->h.n_var))
+        return fail(PH_EINVAL, "start system shape differs from target");
+    if (!start && t && target->h.n_eq != target->h.n_var)
+        return fail(PH_EINVAL, "the total-degree start system needs a square target");
+    if (t && !gamma) return fail(PH_EINVAL, "gamma is null");
+    const DevTable *tab = nullptr;
+    int rc = get_table(target, start, &tab);
+    if (rc) return rc;
+    return eval_launch(*tab, gamma, prec, npts, t, x, ld, val, jac, (hipStream_t)stream);
+}

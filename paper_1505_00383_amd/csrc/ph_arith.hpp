@@ -1,0 +1,350 @@
+// ph_arith.hpp -- complex double, double double and quad double arithmetic for
+// gfx950, the three precisions of the paper (Section 1: DD and QD make the
+// evaluation compute bound).  Written from the published error-free
+// transformations:
+//   * TwoSum (Knuth): s + e = a + b exactly, 6 FP64 operations;
+//   * FastTwoSum (Dekker): the same in 3 operations when |a| >= |b| or a = 0;
+//   * TwoProd with a fused multiply-add: p + e = a * b exactly, 2 operations.
+// A DD number is hi + lo with |lo| <= ulp(hi)/2 (roughly); a QD number is four
+// such limbs.  DD addition is the accurate two-TwoSum form; DD multiplication
+// adds the cross products into the FMA error term (Joldes-Muller-Popescu,
+// "Tight and rigorous error bounds for basic building blocks of double-word
+// arithmetic", 2017, bounds of a few u^2).  QD follows the level-by-level
+// scheme of Hida, Li and Bailey ("Algorithms for quad-double precision
+// floating point arithmetic", 2001): partial products / sums are grouped by
+// their order of magnitude (eps^0, eps^1, ...), each level is summed with
+// TwoSum chains whose errors flow to the next level, and the result is
+// renormalised; terms below eps^4 are dropped.  Relative error per operation
+// stays near 2^-205, far below the parity bar (1e-52 ~ 2^-172).
+//
+// Compile with -ffp-contract=off: every FMA below is explicit and every other
+// operation must round separately for the transformations to be exact.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#define PH_HD __host__ __device__ __forceinline__
+
+namespace ph {
+
+PH_HD void two_sum(double a, double b, double &s, double &e)
+{
+    s = a + b;
+    double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+PH_HD void fast_two_sum(double a, double b, double &s, double &e)
+{
+    s = a + b;
+    e = b - (s - a);
+}
+
+PH_HD void two_prod(double a, double b, double &p, double &e)
+{
+    p = a * b;
+    e = __builtin_fma(a, b, -p);
+}
+
+// ---------------------------------------------------------------------------
+// L-limb reals
+// ---------------------------------------------------------------------------
+template <int L>
+struct R {
+    double v[L];
+};
+
+template <int L>
+PH_HD R<L> r_zero()
+{
+    R<L> r;
+#pragma unroll
+    for (int l = 0; l < L; ++l) r.v[l] = 0.0;
+    return r;
+}
+
+template <int L>
+PH_HD R<L> r_from(double a)
+{
+    R<L> r = r_zero<L>();
+    r.v[0] = a;
+    return r;
+}
+
+template <int L>
+PH_HD R<L> r_neg(R<L> a)
+{
+#pragma unroll
+    for (int l = 0; l < L; ++l) a.v[l] = -a.v[l];
+    return a;
+}
+
+// Renormalise five level-ordered components (c0 of order 1, c_k of order
+// eps^k) into four limbs.  Pass 1 runs FastTwoSum from the bottom up, which
+// leaves c0 = the rounded total and every c_k a rounding error no larger than
+// half an ulp of the partial sum above it; pass 2 runs TwoSum over c1..c4
+// from the bottom up, which closes any gap (a tiny c1 above a larger c2) so
+// that |c_{k+1}| <= ulp(c_k).  The last component is folded in rounded.
+PH_HD R<4> qd_renorm(double c0, double c1, double c2, double c3, double c4)
+{
+    double s;
+    fast_two_sum(c3, c4, s, c4);
+    fast_two_sum(c2, s, s, c3);
+    fast_two_sum(c1, s, s, c2);
+    fast_two_sum(c0, s, c0, c1);
+    two_sum(c3, c4, s, c4);
+    two_sum(c2, s, s, c3);
+    two_sum(c1, s, c1, c2);
+    c3 += c4;
+    R<4> r;
+    r.v[0] = c0;
+    r.v[1] = c1;
+    r.v[2] = c2;
+    r.v[3] = c3;
+    return r;
+}
+
+// The same when cancellation may have left a leading component smaller than a
+// trailing one (after a subtraction): TwoSum in both passes.
+PH_HD R<4> qd_renorm_safe(double c0, double c1, double c2, double c3, double c4)
+{
+    double s;
+    two_sum(c3, c4, s, c4);
+    two_sum(c2, s, s, c3);
+    two_sum(c1, s, s, c2);
+    two_sum(c0, s, c0, c1);
+    two_sum(c3, c4, s, c4);
+    two_sum(c2, s, s, c3);
+    two_sum(c1, s, c1, c2);
+    c3 += c4;
+    R<4> r;
+    r.v[0] = c0;
+    r.v[1] = c1;
+    r.v[2] = c2;
+    r.v[3] = c3;
+    return r;
+}
+
+template <int L>
+PH_HD R<L> r_add(R<L> a, R<L> b)
+{
+    if constexpr (L == 1) {
+        return R<1>{{a.v[0] + b.v[0]}};
+    } else if constexpr (L == 2) {
+        double s, e, t, f;
+        two_sum(a.v[0], b.v[0], s, e);
+        two_sum(a.v[1], b.v[1], t, f);
+        e += t;
+        fast_two_sum(s, e, s, e);
+        e += f;
+        fast_two_sum(s, e, s, e);
+        return R<2>{{s, e}};
+    } else {
+        // level 0..3 pairwise sums; errors flow one level down
+        double s0, e0, s1, e1, s2, e2, s3, e3;
+        two_sum(a.v[0], b.v[0], s0, e0);
+        two_sum(a.v[1], b.v[1], s1, e1);
+        two_sum(a.v[2], b.v[2], s2, e2);
+        two_sum(a.v[3], b.v[3], s3, e3);
+        double u, w;
+        two_sum(s1, e0, s1, u);      // level 1; u -> level 2
+        two_sum(s2, e1, s2, w);      // level 2; w -> level 3
+        two_sum(s2, u, s2, u);       // u -> level 3
+        double x;
+        two_sum(s3, e2, s3, x);      // level 3; x -> level 4
+        two_sum(s3, w, s3, w);
+        two_sum(s3, u, s3, u);
+        double c4 = e3 + x + w + u;  // level 4 (only its leading bits survive)
+        return qd_renorm_safe(s0, s1, s2, s3, c4);
+    }
+}
+
+template <int L>
+PH_HD R<L> r_sub(R<L> a, R<L> b)
+{
+    return r_add<L>(a, r_neg<L>(b));
+}
+
+template <int L>
+PH_HD R<L> r_mul(R<L> a, R<L> b)
+{
+    if constexpr (L == 1) {
+        return R<1>{{a.v[0] * b.v[0]}};
+    } else if constexpr (L == 2) {
+        double p, e;
+        two_prod(a.v[0], b.v[0], p, e);
+        e = __builtin_fma(a.v[0], b.v[1], e);
+        e = __builtin_fma(a.v[1], b.v[0], e);
+        fast_two_sum(p, e, p, e);
+        return R<2>{{p, e}};
+    } else {
+        double p00, q00, p01, q01, p10, q10, p02, q02, p11, q11, p20, q20;
+        two_prod(a.v[0], b.v[0], p00, q00);
+        two_prod(a.v[0], b.v[1], p01, q01);
+        two_prod(a.v[1], b.v[0], p10, q10);
+        two_prod(a.v[0], b.v[2], p02, q02);
+        two_prod(a.v[1], b.v[1], p11, q11);
+        two_prod(a.v[2], b.v[0], p20, q20);
+        // level 3: products of order eps^3 (rounded) and the level-2 errors
+        double c3 = __builtin_fma(a.v[0], b.v[3], a.v[1] * b.v[2]);
+        c3 = __builtin_fma(a.v[2], b.v[1], c3);
+        c3 = __builtin_fma(a.v[3], b.v[0], c3);
+        c3 += q02 + q11 + q20;
+        // level 1: p01 + p10 + q00
+        double c1, u1, u2;
+        two_sum(p01, p10, c1, u1);
+        two_sum(c1, q00, c1, u2);
+        // level 2: p02 + p11 + p20 + q01 + q10 + u1 + u2
+        double c2, w0, w1, w2, w3, w4, w5;
+        two_sum(p02, p11, c2, w0);
+        two_sum(c2, p20, c2, w1);
+        two_sum(c2, q01, c2, w2);
+        two_sum(c2, q10, c2, w3);
+        two_sum(c2, u1, c2, w4);
+        two_sum(c2, u2, c2, w5);
+        c3 += ((w0 + w1) + (w2 + w3)) + (w4 + w5);
+        return qd_renorm(p00, c1, c2, c3, 0.0);
+    }
+}
+
+// a * b with b a double
+template <int L>
+PH_HD R<L> r_mul_d(R<L> a, double b)
+{
+    if constexpr (L == 1) {
+        return R<1>{{a.v[0] * b}};
+    } else if constexpr (L == 2) {
+        double p, e;
+        two_prod(a.v[0], b, p, e);
+        e = __builtin_fma(a.v[1], b, e);
+        fast_two_sum(p, e, p, e);
+        return R<2>{{p, e}};
+    } else {
+        double p0, q0, p1, q1, p2, q2;
+        two_prod(a.v[0], b, p0, q0);
+        two_prod(a.v[1], b, p1, q1);
+        two_prod(a.v[2], b, p2, q2);
+        double c3 = __builtin_fma(a.v[3], b, q2);
+        double c1, u, c2, w0, w1;
+        two_sum(p1, q0, c1, u);
+        two_sum(p2, q1, c2, w0);
+        two_sum(c2, u, c2, w1);
+        c3 += w0 + w1;
+        return qd_renorm(p0, c1, c2, c3, 0.0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// L-limb complex numbers
+// ---------------------------------------------------------------------------
+template <int L>
+struct C {
+    R<L> re, im;
+};
+
+template <int L>
+PH_HD C<L> c_zero()
+{
+    return C<L>{r_zero<L>(), r_zero<L>()};
+}
+
+template <int L>
+PH_HD C<L> c_from(double re, double im)
+{
+    return C<L>{r_from<L>(re), r_from<L>(im)};
+}
+
+template <int L>
+PH_HD C<L> c_add(C<L> a, C<L> b)
+{
+    return C<L>{r_add<L>(a.re, b.re), r_add<L>(a.im, b.im)};
+}
+
+template <int L>
+PH_HD C<L> c_sub(C<L> a, C<L> b)
+{
+    return C<L>{r_sub<L>(a.re, b.re), r_sub<L>(a.im, b.im)};
+}
+
+// Complex product.  Double: four FMA-style operations.  Double double: each
+// component a*b - c*d is formed from the two leading exact products (TwoProd)
+// combined by one TwoSum, the four cross terms and the two product errors
+// folded into the error term, then one FastTwoSum.  Quad double: four
+// products and two sums.
+template <int L>
+PH_HD C<L> c_mul(C<L> a, C<L> b)
+{
+    if constexpr (L == 1) {
+        double re = __builtin_fma(a.re.v[0], b.re.v[0], -(a.im.v[0] * b.im.v[0]));
+        double im = __builtin_fma(a.re.v[0], b.im.v[0], a.im.v[0] * b.re.v[0]);
+        return C<1>{{{re}}, {{im}}};
+    } else if constexpr (L == 2) {
+        C<2> r;
+        {
+            double p1, e1, p2, e2, s, e;
+            two_prod(a.re.v[0], b.re.v[0], p1, e1);
+            two_prod(a.im.v[0], b.im.v[0], p2, e2);
+            two_sum(p1, -p2, s, e);
+            e += e1 - e2;
+            e = __builtin_fma(a.re.v[0], b.re.v[1], e);
+            e = __builtin_fma(a.re.v[1], b.re.v[0], e);
+            e = __builtin_fma(-a.im.v[0], b.im.v[1], e);
+            e = __builtin_fma(-a.im.v[1], b.im.v[0], e);
+            fast_two_sum(s, e, r.re.v[0], r.re.v[1]);
+        }
+        {
+            double p1, e1, p2, e2, s, e;
+            two_prod(a.re.v[0], b.im.v[0], p1, e1);
+            two_prod(a.im.v[0], b.re.v[0], p2, e2);
+            two_sum(p1, p2, s, e);
+            e += e1 + e2;
+            e = __builtin_fma(a.re.v[0], b.im.v[1], e);
+            e = __builtin_fma(a.re.v[1], b.im.v[0], e);
+            e = __builtin_fma(a.im.v[0], b.re.v[1], e);
+            e = __builtin_fma(a.im.v[1], b.re.v[0], e);
+            fast_two_sum(s, e, r.im.v[0], r.im.v[1]);
+        }
+        return r;
+    } else {
+        R<4> rr = r_mul<4>(a.re, b.re), ii = r_mul<4>(a.im, b.im);
+        R<4> ri = r_mul<4>(a.re, b.im), ir = r_mul<4>(a.im, b.re);
+        return C<4>{r_sub<4>(rr, ii), r_add<4>(ri, ir)};
+    }
+}
+
+// complex times real L-limb
+template <int L>
+PH_HD C<L> c_mul_r(C<L> a, R<L> s)
+{
+    return C<L>{r_mul<L>(a.re, s), r_mul<L>(a.im, s)};
+}
+
+// complex times a double (exact scalings by small integers included)
+template <int L>
+PH_HD C<L> c_mul_d(C<L> a, double s)
+{
+    return C<L>{r_mul_d<L>(a.re, s), r_mul_d<L>(a.im, s)};
+}
+
+// L-limb complex times an FP64 complex (coefficients of a system are FP64)
+template <int L>
+PH_HD C<L> c_mul_c64(C<L> a, double br, double bi)
+{
+    if constexpr (L == 1) {
+        double re = __builtin_fma(a.re.v[0], br, -(a.im.v[0] * bi));
+        double im = __builtin_fma(a.re.v[0], bi, a.im.v[0] * br);
+        return C<1>{{{re}}, {{im}}};
+    } else {
+        return C<L>{r_sub<L>(r_mul_d<L>(a.re, br), r_mul_d<L>(a.im, bi)),
+                    r_add<L>(r_mul_d<L>(a.re, bi), r_mul_d<L>(a.im, br))};
+    }
+}
+
+// Leading limb (the FP64 value handed to the FP64 corrector).
+template <int L>
+PH_HD double r_hi(R<L> a)
+{
+    return a.v[0];
+}
+
+} // namespace ph

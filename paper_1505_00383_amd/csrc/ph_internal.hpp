@@ -1,0 +1,81 @@
+// ph_internal.hpp -- internal structures shared by the system compiler, the
+// evaluation kernels and the tracker.  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ph.h"
+
+namespace ph {
+
+// Error reporting: the message of the last failure on this thread.
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int hip_fail(hipError_t e, const char *what);
+
+#define PH_HIP(call)                                     \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) return ph::hip_fail(e_, #call); \
+    } while (0)
+
+// Factor word of the term tables: variable in bits 0..15, exponent in bits
+// 16..30, bit 31 set when this factor is the first contribution of its
+// equation to that Jacobian column (the kernel then stores instead of adding).
+constexpr uint32_t FAC_FIRST = 0x80000000u;
+__host__ __device__ inline int fac_var(uint32_t w) { return int(w & 0xffffu); }
+__host__ __device__ inline int fac_exp(uint32_t w) { return int((w >> 16) & 0x7fffu); }
+
+// Term descriptor: {k = number of factors, offset of the first factor word,
+// sel = 0 for a target term (coefficient scaled by t) or 1 for a start-system
+// term (scaled by gamma (1 - t)), unused}.
+//
+// One "homotopy table" is the merged term stream of target and start system,
+// equation by equation: the instruction stream that every lane of a wave runs
+// on its own point (Section 3: all threads of a block evaluate the same
+// monomial at different points).
+struct DevTable {
+    int n_eq = 0, n_var = 0, kmax = 0;
+    int64_t n_terms = 0, n_fac = 0;
+    int32_t *eq_off = nullptr;   // [n_eq + 1]
+    int4 *tdesc = nullptr;       // [n_terms]
+    uint32_t *fac = nullptr;     // [n_fac]
+    double *coef = nullptr;      // [n_terms][2][4] limbs
+    int32_t *zc_off = nullptr;   // [n_eq + 1] columns of each row no term touches
+    int32_t *zc = nullptr;
+    void *block = nullptr;       // single device allocation holding all of the above
+};
+
+struct HostSystem {
+    int n_eq = 0, n_var = 0, max_k = 0;
+    std::vector<int32_t> eq_term_off, term_fac_off, fac_var, fac_exp, deg;
+    std::vector<double> coef;  // [T][2][4]
+};
+
+struct ph_system_impl;
+
+}  // namespace ph
+
+struct ph_system {
+    ph::HostSystem h;
+    ph::DevTable total;  // target merged with the total-degree start system
+    std::mutex mu;
+    std::map<const ph_system *, ph::DevTable> with_start;  // custom start systems
+    int device = 0;
+};
+
+namespace ph {
+// Build and upload the merged table of (f, g); g == nullptr selects the
+// total-degree start system g_i = x_i^{d_i} - 1.
+int build_table(const HostSystem &f, const HostSystem *g, DevTable &out);
+void free_table(DevTable &t);
+// Table for (target, start), built on first use and cached in the target.
+int get_table(const ph_system *target, const ph_system *start, const DevTable **out);
+}  // namespace ph

@@ -1,0 +1,303 @@
+// system.cpp -- the system compiler: sparse supports and coefficients to the
+// device term tables ("instructions" idx and cff of Table 8 in the paper).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+
+#include "ph_internal.hpp"
+
+namespace ph {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? PH_ENOMEM : PH_EHIP;
+}
+
+void free_table(DevTable &t)
+{
+    if (t.block) (void)hipFree(t.block);
+    t = DevTable{};
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
+{
+    const int ne = f.n_eq, nv = f.n_var;
+    std::vector<int32_t> eq_off(ne + 1, 0), zc_off(ne + 1, 0), zc;
+    std::vector<int4> tdesc;
+    std::vector<uint32_t> fac;
+    std::vector<double> coef;
+    int kmax = 0;
+    std::vector<char> touched(nv);
+    auto emit = [&](const HostSystem &s, int i, int sel) {
+        for (int t = s.eq_term_off[i]; t < s.eq_term_off[i + 1]; ++t) {
+            int a = s.term_fac_off[t], b = s.term_fac_off[t + 1];
+            int4 d;
+            d.x = b - a;
+            d.y = int(fac.size());
+            d.z = sel;
+            d.w = 0;
+            tdesc.push_back(d);
+            kmax = std::max(kmax, b - a);
+            for (int q = a; q < b; ++q) {
+                uint32_t w = uint32_t(s.fac_var[q]) | (uint32_t(s.fac_exp[q]) << 16);
+                if (!touched[s.fac_var[q]]) {
+                    w |= FAC_FIRST;
+                    touched[s.fac_var[q]] = 1;
+                }
+                fac.push_back(w);
+            }
+            for (int c = 0; c < 8; ++c) coef.push_back(s.coef[size_t(t) * 8 + c]);
+        }
+    };
+    for (int i = 0; i < ne; ++i) {
+        std::fill(touched.begin(), touched.end(), 0);
+        emit(f, i, 0);
+        if (g) {
+            emit(*g, i, 1);
+        } else {
+            // g_i = x_i^{d_i} - 1: one term x_i^{d_i} (coefficient 1), one constant
+            // -1.  Defined for square systems only; g_i = 0 when d_i = 0.
+            int d = f.deg[i];
+            if (ne == nv && d > 0) {
+                int4 t1;
+                t1.x = 1;
+                t1.y = int(fac.size());
+                t1.z = 1;
+                t1.w = 0;
+                tdesc.push_back(t1);
+                uint32_t w = uint32_t(i) | (uint32_t(d) << 16);
+                if (!touched[i]) {
+                    w |= FAC_FIRST;
+                    touched[i] = 1;
+                }
+                fac.push_back(w);
+                double one[8] = {1, 0, 0, 0, 0, 0, 0, 0};
+                coef.insert(coef.end(), one, one + 8);
+                kmax = std::max(kmax, 1);
+            }
+            if (ne == nv && d > 0) {
+                int4 t0;
+                t0.x = 0;
+                t0.y = int(fac.size());
+                t0.z = 1;
+                t0.w = 0;
+                tdesc.push_back(t0);
+                double m1[8] = {-1, 0, 0, 0, 0, 0, 0, 0};
+                coef.insert(coef.end(), m1, m1 + 8);
+            }
+        }
+        eq_off[i + 1] = int32_t(tdesc.size());
+        for (int j = 0; j < nv; ++j)
+            if (!touched[j]) zc.push_back(j);
+        zc_off[i + 1] = int32_t(zc.size());
+    }
+    if (tdesc.empty()) {  // keep every pointer valid
+        tdesc.push_back(int4{0, 0, 0, 0});
+        coef.resize(8, 0.0);
+    }
+    if (fac.empty()) fac.push_back(0);
+    if (zc.empty()) zc.push_back(0);
+
+    size_t o_eq = 0;
+    size_t o_td = o_eq + align256(eq_off.size() * 4);
+    size_t o_fac = o_td + align256(tdesc.size() * sizeof(int4));
+    size_t o_cf = o_fac + align256(fac.size() * 4);
+    size_t o_zo = o_cf + align256(coef.size() * 8);
+    size_t o_zc = o_zo + align256(zc_off.size() * 4);
+    size_t total = o_zc + align256(zc.size() * 4);
+    std::vector<char> host(total, 0);
+    std::memcpy(host.data() + o_eq, eq_off.data(), eq_off.size() * 4);
+    std::memcpy(host.data() + o_td, tdesc.data(), tdesc.size() * sizeof(int4));
+    std::memcpy(host.data() + o_fac, fac.data(), fac.size() * 4);
+    std::memcpy(host.data() + o_cf, coef.data(), coef.size() * 8);
+    std::memcpy(host.data() + o_zo, zc_off.data(), zc_off.size() * 4);
+    std::memcpy(host.data() + o_zc, zc.data(), zc.size() * 4);
+    char *dev = nullptr;
+    PH_HIP(hipMalloc(&dev, total));
+    hipError_t e = hipMemcpy(dev, host.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(dev);
+        return hip_fail(e, "hipMemcpy(term tables)");
+    }
+    out.n_eq = ne;
+    out.n_var = nv;
+    out.kmax = kmax;
+    out.n_terms = int64_t(tdesc.size());
+    out.n_fac = int64_t(fac.size());
+    out.block = dev;
+    out.eq_off = reinterpret_cast<int32_t *>(dev + o_eq);
+    out.tdesc = reinterpret_cast<int4 *>(dev + o_td);
+    out.fac = reinterpret_cast<uint32_t *>(dev + o_fac);
+    out.coef = reinterpret_cast<double *>(dev + o_cf);
+    out.zc_off = reinterpret_cast<int32_t *>(dev + o_zo);
+    out.zc = reinterpret_cast<int32_t *>(dev + o_zc);
+    return PH_OK;
+}
+
+int get_table(const ph_system *target, const ph_system *start, const DevTable **out)
+{
+    if (!start) {
+        *out = &target->total;
+        return PH_OK;
+    }
+    ph_system *t = const_cast<ph_system *>(target);
+    std::lock_guard<std::mutex> lk(t->mu);
+    auto it = t->with_start.find(start);
+    if (it != t->with_start.end()) {
+        *out = &it->second;
+        return PH_OK;
+    }
+    DevTable tab;
+    int rc = build_table(target->h, &start->h, tab);
+    if (rc) return rc;
+    auto res = t->with_start.emplace(start, tab);
+    *out = &res.first->second;
+    return PH_OK;
+}
+
+static int validate(int32_t n_eq, int32_t n_var, const int32_t *eq_term_off,
+                    const int32_t *term_fac_off, const int32_t *fac_var, const int32_t *fac_exp,
+                    const double *coef, int32_t coef_limbs)
+{
+    if (n_var < 1 || n_eq < 1) return fail(PH_EINVAL, "n_eq and n_var must be >= 1");
+    if (n_var > 64 || n_eq > 64) return fail(PH_EUNSUPPORTED, "n_eq and n_var are limited to 64");
+    if (n_var > n_eq) return fail(PH_EINVAL, "n_var must not exceed n_eq (least squares needs m >= n)");
+    if (!eq_term_off || !term_fac_off || !coef)
+        return fail(PH_EINVAL, "null system array");
+    if (coef_limbs != 1 && coef_limbs != 2 && coef_limbs != 4)
+        return fail(PH_EINVAL, "coef_limbs must be 1, 2 or 4");
+    if (eq_term_off[0] != 0) return fail(PH_EINVAL, "eq_term_off[0] must be 0");
+    for (int i = 0; i < n_eq; ++i)
+        if (eq_term_off[i + 1] < eq_term_off[i]) return fail(PH_EINVAL, "eq_term_off not monotone");
+    int64_t T = eq_term_off[n_eq];
+    if (term_fac_off[0] != 0) return fail(PH_EINVAL, "term_fac_off[0] must be 0");
+    for (int64_t t = 0; t < T; ++t) {
+        int a = term_fac_off[t], b = term_fac_off[t + 1];
+        if (b < a) return fail(PH_EINVAL, "term_fac_off not monotone");
+        if (b - a > 32) return fail(PH_EUNSUPPORTED, "a term has more than 32 factors");
+        for (int q = a; q < b; ++q) {
+            if (!fac_var || !fac_exp) return fail(PH_EINVAL, "null factor array");
+            if (fac_var[q] < 0 || fac_var[q] >= n_var)
+                return fail(PH_EINVAL, "factor variable out of range");
+            if (q > a && fac_var[q] <= fac_var[q - 1])
+                return fail(PH_EINVAL, "factor variables must strictly increase within a term");
+            if (fac_exp[q] < 1 || fac_exp[q] > 64)
+                return fail(PH_EINVAL, "factor exponent must be in 1..64");
+        }
+    }
+    return PH_OK;
+}
+
+}  // namespace ph
+
+using namespace ph;
+
+extern "C" int ph_system_create(int32_t n_eq, int32_t n_var, const int32_t *eq_term_off,
+                                const int32_t *term_fac_off, const int32_t *fac_var,
+                                const int32_t *fac_exp, const double *coef, int32_t coef_limbs,
+                                ph_system **out)
+{
+    if (!out) return fail(PH_EINVAL, "out is null");
+    *out = nullptr;
+    int rc = validate(n_eq, n_var, eq_term_off, term_fac_off, fac_var, fac_exp, coef, coef_limbs);
+    if (rc) return rc;
+    std::unique_ptr<ph_system> s(new ph_system());
+    HostSystem &h = s->h;
+    h.n_eq = n_eq;
+    h.n_var = n_var;
+    int64_t T = eq_term_off[n_eq];
+    int64_t F = term_fac_off[T];
+    h.eq_term_off.assign(eq_term_off, eq_term_off + n_eq + 1);
+    h.term_fac_off.assign(term_fac_off, term_fac_off + T + 1);
+    if (F > 0) {
+        h.fac_var.assign(fac_var, fac_var + F);
+        h.fac_exp.assign(fac_exp, fac_exp + F);
+    }
+    h.coef.assign(size_t(T) * 8, 0.0);
+    for (int64_t t = 0; t < T; ++t)
+        for (int c = 0; c < 2; ++c)
+            for (int l = 0; l < coef_limbs; ++l)
+                h.coef[size_t(t) * 8 + c * 4 + l] = coef[(size_t(t) * 2 + c) * coef_limbs + l];
+    h.deg.assign(n_eq, 0);
+    for (int i = 0; i < n_eq; ++i) {
+        int best = 0;
+        for (int t = eq_term_off[i]; t < eq_term_off[i + 1]; ++t) {
+            int d = 0;
+            for (int q = term_fac_off[t]; q < term_fac_off[t + 1]; ++q) d += fac_exp[q];
+            best = std::max(best, d);
+            h.max_k = std::max(h.max_k, term_fac_off[t + 1] - term_fac_off[t]);
+        }
+        h.deg[i] = best;
+    }
+    PH_HIP(hipGetDevice(&s->device));
+    rc = build_table(h, nullptr, s->total);
+    if (rc) return rc;
+    *out = s.release();
+    return PH_OK;
+}
+
+extern "C" int ph_system_destroy(ph_system *s)
+{
+    if (!s) return fail(PH_EINVAL, "null system");
+    (void)hipDeviceSynchronize();
+    free_table(s->total);
+    for (auto &kv : s->with_start) free_table(kv.second);
+    delete s;
+    return PH_OK;
+}
+
+extern "C" int ph_system_info(const ph_system *s, int32_t *n_eq, int32_t *n_var, int64_t *n_terms,
+                              int32_t *max_factors)
+{
+    if (!s) return fail(PH_EINVAL, "null system");
+    if (n_eq) *n_eq = s->h.n_eq;
+    if (n_var) *n_var = s->h.n_var;
+    if (n_terms) *n_terms = s->h.eq_term_off.back();
+    if (max_factors) *max_factors = s->h.max_k;
+    return PH_OK;
+}
+
+extern "C" int ph_system_degrees(const ph_system *s, int32_t *deg)
+{
+    if (!s || !deg) return fail(PH_EINVAL, "null argument");
+    for (int i = 0; i < s->h.n_eq; ++i) deg[i] = s->h.deg[i];
+    return PH_OK;
+}
+
+extern "C" const char *ph_last_error(void) { return g_err.c_str(); }
+
+extern "C" int ph_track_opts_default(ph_track_opts *o)
+{
+    if (!o) return fail(PH_EINVAL, "null opts");
+    o->prec = PH_D;
+    o->mixed = 0;
+    o->predictor_order = 1;
+    o->max_newton = 3;
+    o->expand_after = 3;
+    o->polish_max = 8;
+    o->h_init = 0.01;
+    o->h_min = 1e-10;
+    o->h_max = 0.1;
+    o->shrink = 0.5;
+    o->expand = 1.5;
+    o->tol_dx = 1e-8;
+    o->diverge_norm = 1e8;
+    o->polish_tol = -1.0;
+    o->max_steps = 100000;
+    return PH_OK;
+}

@@ -1,0 +1,206 @@
+"""GPU parity of ph_eval_jac (and the device arithmetic) against the oracle.
+
+Every comparison goes through the C ABI.  Tolerance: |gpu - oracle| <= tol * S
+per entry (tests/parity.py).  Cases: a small system over several 64-point
+tiles with a ragged tail, the full evaluation workload (n = 32, 64 terms per
+equation, k = 8, 65536 points) sampled at points the oracle computes one by
+one, t = 1 (target only), an explicit start system, long terms (k up to 20),
+a least-squares shaped system, npts = 0 / 1 and ld > npts.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1505_00383_amd as ph
+from paper_1505_00383_amd import synth
+from tests.exact import fr, frc
+from tests.parity import TOL, scaled_error
+
+pytestmark = pytest.mark.gpu
+
+LIMBS = [1, 2, 4]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print(f"\n[gpu] device: {torch.cuda.get_device_name(0)}", flush=True)
+
+
+def _run(sysm, L, x, t, gamma, start=None, jac=True, ld=None):
+    S = ph.System(sysm)
+    G = ph.System(start) if start is not None else None
+    import torch
+    npts = x.shape[0]
+    xs = ph.to_soa(x, ld)
+    tt = None if t is None else torch.as_tensor(np.ascontiguousarray(t), dtype=torch.float64).cuda()
+    val, jm = ph.eval_jac(S, xs, npts, L, tt, gamma, start=G, want_jac=jac)
+    torch.cuda.synchronize()
+    v = ph.from_soa(val, npts, (sysm.n_eq, 2, L))
+    j = ph.from_soa(jm, npts, (sysm.n_eq, sysm.n_var, 2, L)) if jac else None
+    return v, j
+
+
+def _check(sysm, L, x, t, gamma, start=None, jac=True, ld=None, threads=8):
+    v, j = _run(sysm, L, x, t, gamma, start, jac, ld)
+    ov, oj, sv, sj = oracle.eval_homotopy(sysm, L, x, t, gamma, start=start, jac=jac)
+    ev = scaled_error(v, ov, sv)
+    ej = scaled_error(j, oj, sj) if jac else 0.0
+    print(f"[gpu] {sysm.name or 'system'} L={L} npts={x.shape[0]} val_err/S={ev:.2e} "
+          f"jac_err/S={ej:.2e}", flush=True)
+    assert ev <= TOL[L] and ej <= TOL[L]
+    return ev, ej
+
+
+@pytest.mark.parametrize("L", LIMBS)
+def test_arith_probe_exact(L):
+    rng = np.random.default_rng(L)
+    n = 500
+    a = np.zeros((n, L))
+    b = np.zeros((n, L))
+    for arr in (a, b):
+        arr[:, 0] = rng.normal(size=n) * 2.0 ** rng.integers(-20, 20, size=n)
+        for l in range(1, L):
+            arr[:, l] = rng.uniform(-0.5, 0.5, n) * np.spacing(np.abs(arr[:, l - 1]))
+    b[::7] = -a[::7]            # exact cancellation
+    # heavy cancellation with normalised operands: b = -(a0 + a1/2 + a2/2 ...)
+    b[1::7, 0] = -a[1::7, 0]
+    b[1::7, 1:] = -0.5 * a[1::7, 1:]
+    bound = {1: 2.0 ** -53, 2: 2.0 ** -101, 4: 2.0 ** -200}[L]
+    for op, f in ((0, lambda x, y: x + y), (1, lambda x, y: x - y), (2, lambda x, y: x * y)):
+        out = ph.arith_probe(L, op, a, b)
+        for i in range(n):
+            ex = f(fr(a[i]), fr(b[i]))
+            got = fr(out[i])
+            scale = abs(fr(a[i])) + abs(fr(b[i])) if op < 2 else abs(ex)
+            assert abs(got - ex) <= Fraction(bound) * scale, (op, i)
+    # complex multiply: componentwise error relative to |ar br| + |ai bi| etc.
+    ca = np.stack([a, np.roll(a, 1, 0)], 1)
+    cb = np.stack([b, np.roll(b, 3, 0)], 1)
+    out = ph.arith_probe(L, 4, ca, cb)
+    cbound = {1: 2.0 ** -52, 2: 2.0 ** -100, 4: 2.0 ** -198}[L]
+    for i in range(0, n, 5):
+        ar, ai = frc(ca[i])
+        br, bi = frc(cb[i])
+        gr, gi = frc(out[i])
+        assert abs(gr - (ar * br - ai * bi)) <= Fraction(cbound) * (abs(ar * br) + abs(ai * bi))
+        assert abs(gi - (ar * bi + ai * br)) <= Fraction(cbound) * (abs(ar * bi) + abs(ai * br))
+
+
+@pytest.mark.parametrize("L", LIMBS)
+def test_eval_multi_tile_ragged(L):
+    s = synth.eval_dense(seed=777, n=8, terms_per_eq=12, k=4)
+    rng = np.random.default_rng(5)
+    npts = 64 * 4 + 37
+    x = synth.random_points(8, npts, L, rng, 0.9)
+    t = rng.uniform(0, 1, npts)
+    _check(s, L, x, t, synth.gamma_of(s))
+
+
+@pytest.mark.parametrize("L", LIMBS)
+def test_eval_full_workload_sampled(L):
+    """n = 32, 64 terms per equation over k = 8 variables, exponents 1..3,
+    65536 points on the unit torus, t ~ U[0,1): the benchmark launch; the
+    oracle recomputes a sample of points including the first and the last."""
+    import torch
+    s = synth.eval_dense()
+    npts = 65536
+    x, t = synth.torus_points(s, npts, L)
+    S = ph.System(s)
+    xs = ph.to_soa(x)
+    tt = torch.as_tensor(t, dtype=torch.float64).cuda()
+    val, jm = ph.eval_jac(S, xs, npts, L, tt, synth.gamma_of(s))
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(val).all()) and bool(torch.isfinite(jm).all())
+    nsamp = {1: 12, 2: 6, 4: 3}[L]
+    idx = np.unique(np.concatenate([[0, 63, 64, npts - 1],
+                                    np.random.default_rng(9).integers(0, npts, nsamp)]))
+    it = torch.as_tensor(idx, device="cuda")
+    v = val[:, it].T.contiguous().cpu().numpy().reshape(len(idx), s.n_eq, 2, L)
+    j = jm[:, it].T.contiguous().cpu().numpy().reshape(len(idx), s.n_eq, s.n_var, 2, L)
+    ov, oj, sv, sj = oracle.eval_homotopy(s, L, x[idx], t[idx], synth.gamma_of(s))
+    ev, ej = scaled_error(v, ov, sv), scaled_error(j, oj, sj)
+    print(f"[gpu] full L={L} samples={len(idx)} val_err/S={ev:.2e} jac_err/S={ej:.2e}", flush=True)
+    assert ev <= TOL[L] and ej <= TOL[L]
+
+
+@pytest.mark.parametrize("L", LIMBS)
+def test_eval_target_only_and_explicit_start(L):
+    s = synth.tracking_cubic()
+    rng = np.random.default_rng(6)
+    x = synth.random_points(s.n_var, 100, L, rng)
+    _check(s, L, x, None, synth.gamma_of(s))            # t = 1: f alone
+    deg = s.degrees()
+    g = synth.system_from_terms(s.n_var, [[(1.0 + 0.5j, {i: int(deg[i])}), (-1, {}),
+                                            (0.25, {(i + 1) % s.n_var: 1})] for i in range(s.n_eq)])
+    _check(s, L, x, rng.uniform(0, 1, 100), synth.gamma_of(s), start=g)
+
+
+@pytest.mark.parametrize("L", [1, 2])
+def test_eval_long_terms(L):
+    s = synth.eval_dense(seed=31, n=24, terms_per_eq=6, k=20, max_exp=2)
+    rng = np.random.default_rng(8)
+    x = synth.random_points(24, 70, L, rng, 0.95)
+    _check(s, L, x, rng.uniform(0, 1, 70), synth.gamma_of(s))
+
+
+def test_eval_least_squares_shape_and_values_only():
+    rng = np.random.default_rng(12)
+    eqs = []
+    for i in range(7):
+        eqs.append([(synth.unit_complex(rng), {int(v): 1 + int(v) % 2 for v in rng.choice(4, 2, replace=False)}),
+                    (synth.unit_complex(rng), {i % 4: 1}), (synth.unit_complex(rng), {})])
+    s = synth.system_from_terms(4, eqs)
+    x = synth.random_points(4, 90, 2, rng)
+    _check(s, 2, x, None, 1.0)
+    v, j = _run(s, 2, x, None, 1.0, jac=False)
+    ov, _, sv, _ = oracle.eval_homotopy(s, 2, x, None, 1.0, jac=False)
+    assert scaled_error(v, ov, sv) <= TOL[2] and j is None
+
+
+def test_eval_degenerate_sizes():
+    s = synth.tracking_small()
+    rng = np.random.default_rng(13)
+    import torch
+    S = ph.System(s)
+    xs = torch.zeros((s.n_var * 2, 4), dtype=torch.float64, device="cuda")
+    val = torch.full((s.n_eq * 2, 4), 7.0, dtype=torch.float64, device="cuda")
+    ph.eval_jac(S, xs, 0, 1, None, val=val, want_jac=False)   # npts = 0: no-op
+    torch.cuda.synchronize()
+    assert torch.all(val == 7.0)
+    for L in LIMBS:
+        x = synth.random_points(s.n_var, 1, L, rng)
+        _check(s, L, x, np.array([0.3]), synth.gamma_of(s))               # one point
+        x = synth.random_points(s.n_var, 5, L, rng)
+        _check(s, L, x, rng.uniform(0, 1, 5), synth.gamma_of(s), ld=133)  # ld > npts
+
+
+@pytest.mark.parametrize("L", LIMBS)
+def test_start_solutions_match_oracle(L):
+    s = synth.tracking_cubic()
+    S = ph.System(s)
+    n = s.n_var
+    B = 3 ** n
+    xs = ph.start_solutions(S, L, 0, B)
+    import torch
+    torch.cuda.synchronize()
+    X = ph.from_soa(xs, B, (n, 2, L))
+    deg = oracle.degrees(s)
+    for p in list(range(0, B, 97)) + [B - 1]:
+        ref = oracle.start_solution(L, deg, p)
+        d = np.abs(X[p].sum(-1) - ref.sum(-1)).max()
+        assert d <= 2.0 ** (-50 * L) * 4
+        for i in range(n):
+            re, im = frc(X[p, i])
+            pr, pi_ = Fraction(1), Fraction(0)
+            for _ in range(3):
+                pr, pi_ = pr * re - pi_ * im, pr * im + pi_ * re
+            assert abs(pr - 1) <= Fraction(2.0 ** (-50 * L)) and abs(pi_) <= Fraction(2.0 ** (-50 * L))
+    # an offset range gives the same points
+    xs2 = ph.start_solutions(S, L, 100, 50)
+    torch.cuda.synchronize()
+    assert np.array_equal(ph.from_soa(xs2, 50, (n, 2, L)), X[100:150])
