@@ -153,6 +153,56 @@ typedef struct {
 /* Fill *o with the defaults listed above (prec = PH_D, mixed = 0). */
 int ph_track_opts_default(ph_track_opts *o);
 
+/*
+ * ph_track -- track npaths solution paths of gamma (1-t) g + t f = 0 from t = 0
+ * to t = 1 (Section 2, Tables 1-3): per path its own t and step size,
+ * predict (secant; zero order on the first step), evaluate-correct with
+ * Newton steps solved by MGS least squares until converged (at most
+ * max_newton per step), step-size control, status 1 / -1, and a Newton polish
+ * at t = 1.  Paths run in a persistent kernel that refills lanes from a
+ * device work queue as paths end; no host round trip happens until all
+ * paths are done.
+ *   target  : square system f, n <= 32, terms with at most 8 factors
+ *   start   : g, or NULL for the total-degree start g_i = x_i^{d_i} - 1
+ *   gamma   : host {re, im}
+ *   x_start : device SoA start points (rows (i*2+c)*prec+l), or NULL for the
+ *             roots of unity of path indices 0..npaths-1 (start must be NULL)
+ *   ld      : leading dimension of x_start and x_end (>= npaths)
+ *   opts    : see ph_track_opts (prec, mixed, step control)
+ *   x_end   : device SoA endpoints (same layout)
+ *   status  : device int8[npaths], 1 success / -1 failure
+ *   reason  : device int8[npaths] PH_R_* (nullable)
+ *   steps   : device int32[npaths] predictor steps (nullable)
+ *   rep     : host report (nullable)
+ * Synchronous: returns after the stream has finished (it fills rep).
+ * Allocates a few KB of device scratch per call.  Errors: PH_EINVAL,
+ * PH_EUNSUPPORTED (non-square, n > 32, k > 8, predictor_order != 1, degrees
+ * without closed-form roots of unity), PH_ENOMEM, PH_EHIP.
+ */
+int ph_track(const ph_system *target, const ph_system *start, const double gamma[2],
+             int64_t npaths, const double *x_start, int64_t ld, const ph_track_opts *opts,
+             double *x_end, int8_t *status, int8_t *reason, int32_t *steps,
+             ph_track_report *rep, void *stream);
+
+/*
+ * ph_track_batch -- many homotopies in one launch: the paths of nsys target
+ * systems (total-degree start systems, roots-of-unity start points) are
+ * concatenated into one device work queue; system s owns global path indices
+ * path_off[s] .. path_off[s+1]-1.
+ *   targets  : host array of nsys handles (square, n <= 32)
+ *   gammas   : host [nsys][2]
+ *   path_off : host int64[nsys + 1], path_off[0] = 0
+ *   path_ids : host int64[path_off[nsys]] multi-index numbers of the tracked
+ *              start solutions of each system, or NULL (0 .. npaths_s - 1)
+ *   x_end, status, reason, steps : indexed by the global path index (ld >= total)
+ * Lanes per path are the next power of two >= the largest n of the batch.
+ * Same synchrony, scratch and errors as ph_track.
+ */
+int ph_track_batch(int32_t nsys, const ph_system *const *targets, const double *gammas,
+                   const int64_t *path_off, const int64_t *path_ids, const ph_track_opts *opts,
+                   double *x_end, int64_t ld, int8_t *status, int8_t *reason, int32_t *steps,
+                   ph_track_report *rep, void *stream);
+
 /* Message of the last failure on the calling thread ("" if none). */
 const char *ph_last_error(void);
 

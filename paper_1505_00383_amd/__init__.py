@@ -24,7 +24,41 @@ REASONS = {0: "NONE", 1: "SUCCESS", 2: "DIVERGED", 3: "STEP_UNDERFLOW", 4: "MAX_
            5: "SINGULAR", 6: "NAN"}
 EXPORTED = ["ph_system_create", "ph_system_destroy", "ph_system_info", "ph_system_degrees",
             "ph_start_solutions", "ph_eval_jac", "ph_track_opts_default", "ph_last_error",
-            "ph_arith_probe"]
+            "ph_arith_probe", "ph_track", "ph_track_batch"]
+
+
+class TrackOpts(ctypes.Structure):
+    """Mirror of ph_track_opts (include/ph.h)."""
+    _fields_ = [("prec", ctypes.c_int32), ("mixed", ctypes.c_int32),
+                ("predictor_order", ctypes.c_int32), ("max_newton", ctypes.c_int32),
+                ("expand_after", ctypes.c_int32), ("polish_max", ctypes.c_int32),
+                ("h_init", ctypes.c_double), ("h_min", ctypes.c_double),
+                ("h_max", ctypes.c_double), ("shrink", ctypes.c_double),
+                ("expand", ctypes.c_double), ("tol_dx", ctypes.c_double),
+                ("diverge_norm", ctypes.c_double), ("polish_tol", ctypes.c_double),
+                ("max_steps", ctypes.c_int64)]
+
+
+class TrackReport(ctypes.Structure):
+    """Mirror of ph_track_report."""
+    _fields_ = [(n, ctypes.c_int64) for n in ("n_success", "n_fail", "n_diverged",
+                                               "n_step_underflow", "n_max_steps", "n_singular",
+                                               "n_nan", "steps", "rejected", "newton_its")] + \
+               [("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
+def track_opts(**kw) -> TrackOpts:
+    """ph_track_opts_default() with keyword overrides."""
+    o = TrackOpts()
+    _check(load_library().ph_track_opts_default(ctypes.byref(o)))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
 
 
 class PHError(RuntimeError):
@@ -52,6 +86,8 @@ def load_library(path: str = LIB_PATH):
     L.ph_track_opts_default.argtypes = [P]
     L.ph_last_error.restype = ctypes.c_char_p
     L.ph_arith_probe.argtypes = [i32, i32, i64, P, P, P, P]
+    L.ph_track.argtypes = [P, P, P, i64, P, i64, P, P, P, P, P, P, P]
+    L.ph_track_batch.argtypes = [i32, P, P, P, P, P, P, i64, P, P, P, P, P]
     for name in EXPORTED:
         fn = getattr(L, name)
         if name != "ph_last_error":
@@ -196,3 +232,72 @@ def arith_probe(prec: int, op: int, a, b, stream=None):
     _check(load_library().ph_arith_probe(prec, op, at.shape[0], _ptr(at), _ptr(bt), _ptr(out),
                                _stream(stream)))
     return out.cpu().numpy()
+
+
+def _track_outputs(torch, n_rows, total, ld):
+    x_end = torch.zeros((n_rows, max(ld, 1)), dtype=torch.float64, device="cuda")
+    status = torch.zeros(max(total, 1), dtype=torch.int8, device="cuda")
+    reason = torch.zeros(max(total, 1), dtype=torch.int8, device="cuda")
+    steps = torch.zeros(max(total, 1), dtype=torch.int32, device="cuda")
+    return x_end, status, reason, steps
+
+
+def track(sys: System, gamma, npaths: int, opts: TrackOpts | None = None, x_start=None,
+          start: System | None = None, stream=None):
+    """Track paths 0..npaths-1 of gamma(1-t) g + t f (ph_track).  x_start: device SoA
+    start points [n*2*prec, ld] or None (roots of unity).  Returns a dict with
+    device x_end [n*2*prec, ld] and numpy status / reason / steps, plus the report."""
+    torch = _torch()
+    opts = opts or track_opts()
+    L = opts.prec
+    ld = x_start.shape[1] if x_start is not None else max(npaths, 1)
+    x_end, status, reason, steps = _track_outputs(torch, sys.n_var * 2 * L, npaths, ld)
+    rep = TrackReport()
+    g = (ctypes.c_double * 2)(complex(gamma).real, complex(gamma).imag)
+    _check(load_library().ph_track(sys.handle, None if start is None else start.handle, g, npaths,
+                                   _ptr(x_start), ld, ctypes.byref(opts), _ptr(x_end),
+                                   _ptr(status), _ptr(reason), _ptr(steps), ctypes.byref(rep),
+                                   _stream(stream)))
+    return dict(x_end=x_end, status=status[:npaths].cpu().numpy(),
+                reason=reason[:npaths].cpu().numpy(), steps=steps[:npaths].cpu().numpy(),
+                report=rep.as_dict())
+
+
+def track_batch(systems, gammas, path_lists, opts: TrackOpts | None = None, stream=None):
+    """Track the given start-solution indices of several systems in one launch
+    (ph_track_batch).  path_lists[s]: int array of multi-index numbers or None
+    for every start solution of system s.  Global path order = concatenation."""
+    torch = _torch()
+    opts = opts or track_opts()
+    L = opts.prec
+    nsys = len(systems)
+    counts, ids = [], []
+    any_ids = any(p is not None for p in path_lists)
+    for s, p in zip(systems, path_lists):
+        if p is None:
+            B = int(np.prod(s.degrees().astype(np.int64)))
+            counts.append(B)
+            if any_ids:
+                ids.append(np.arange(B, dtype=np.int64))
+        else:
+            p = np.asarray(p, dtype=np.int64)
+            counts.append(len(p))
+            ids.append(p)
+    off = np.zeros(nsys + 1, dtype=np.int64)
+    off[1:] = np.cumsum(counts)
+    total = int(off[-1])
+    pid = np.ascontiguousarray(np.concatenate(ids)) if any_ids else None
+    nmax = max(s.n_var for s in systems)
+    x_end, status, reason, steps = _track_outputs(torch, nmax * 2 * L, total, total)
+    handles = (ctypes.c_void_p * nsys)(*[s.handle.value for s in systems])
+    gam = np.ascontiguousarray([[complex(g).real, complex(g).imag] for g in gammas],
+                               dtype=np.float64)
+    rep = TrackReport()
+    _check(load_library().ph_track_batch(nsys, handles, gam.ctypes.data, off.ctypes.data,
+                                         None if pid is None else pid.ctypes.data,
+                                         ctypes.byref(opts), _ptr(x_end), max(total, 1),
+                                         _ptr(status), _ptr(reason), _ptr(steps),
+                                         ctypes.byref(rep), _stream(stream)))
+    return dict(x_end=x_end, status=status[:total].cpu().numpy(),
+                reason=reason[:total].cpu().numpy(), steps=steps[:total].cpu().numpy(),
+                report=rep.as_dict(), path_off=off)

@@ -28,6 +28,7 @@
 
 #include "ph_arith.hpp"
 #include "ph_internal.hpp"
+#include "ph_sweep.hpp"
 
 namespace ph {
 
@@ -156,50 +157,16 @@ __global__ void __launch_bounds__(512) eval_kernel(EvalArgs a)
                 continue;
             }
             uint32_t fw[KMAX];
-            C<L> xv[KMAX];
-            C<L> q[KMAX];
 #pragma unroll
             for (int l = 0; l < KMAX; ++l)
                 if (l < k) fw[l] = a.fac[d.y + l];
-            // common factor c(t) * prod x^(a-1)
-            C<L> cf = c;
-#pragma unroll
-            for (int l = 0; l < KMAX; ++l) {
-                if (l < k) {
-                    xv[l] = X(fac_var(fw[l]));
-                    const int e = fac_exp(fw[l]);
-                    for (int r = 1; r < e; ++r) cf = c_mul<L>(cf, xv[l]);
-                }
-            }
-            // forward products
-            q[0] = cf;
-#pragma unroll
-            for (int l = 1; l < KMAX; ++l)
-                if (l < k) q[l] = c_mul<L>(q[l - 1], xv[l - 1]);
-            C<L> last = q[0], xlast = xv[0];
-#pragma unroll
-            for (int l = 1; l < KMAX; ++l)
-                if (l == k - 1) {
-                    last = q[l];
-                    xlast = xv[l];
-                }
-            v = c_add<L>(v, c_mul<L>(last, xlast));
-            if constexpr (JAC) {
-                // backward products: partial_l = a_l * q_l * (x_{l+1} ... x_{k-1})
-                C<L> sfx = xlast;
-#pragma unroll
-                for (int l = KMAX - 1; l >= 0; --l) {
-                    if (l < k) {
-                        C<L> part = (l == k - 1) ? q[l] : c_mul<L>(q[l], sfx);
-                        if (l < k - 1 && l > 0) sfx = c_mul<L>(sfx, xv[l]);
-                        const int e = fac_exp(fw[l]);
-                        if (e != 1) part = c_mul_d<L>(part, (double)e);
-                        const int var = fac_var(fw[l]);
-                        jac_acc<L>(jrow0 + (int64_t)var * 2 * L * a.ld, a.ld, (fw[l] & FAC_FIRST) != 0,
-                                   part, act);
-                    }
-                }
-            }
+            const C<L> tv_term = term_sweep<KMAX, JAC>(
+                k, fw, c, X, [&](int, uint32_t w, const C<L> &part) {
+                    if constexpr (JAC)
+                        jac_acc<L>(jrow0 + (int64_t)fac_var(w) * 2 * L * a.ld, a.ld,
+                                   (w & FAC_FIRST) != 0, part, act);
+                });
+            v = c_add<L>(v, tv_term);
         }
         if (act) {
 #pragma unroll

@@ -340,6 +340,93 @@ PH_HD C<L> c_mul_c64(C<L> a, double br, double bi)
     }
 }
 
+// 1/b by Newton's iteration y <- y + y (1 - b y) from the FP64 reciprocal of
+// the leading limb; every step doubles the correct bits (53 -> 106 -> 212).
+template <int L>
+PH_HD R<L> r_recip(R<L> b)
+{
+    R<L> y = r_from<L>(1.0 / b.v[0]);
+    if constexpr (L > 1) {
+        const int steps = L == 2 ? 1 : 2;
+        for (int s = 0; s < steps; ++s) {
+            R<L> e = r_sub<L>(r_from<L>(1.0), r_mul<L>(b, y));
+            y = r_add<L>(y, r_mul<L>(y, e));
+        }
+    }
+    return y;
+}
+
+// a / b = a (1/b) plus one correction term y (a - b q).
+template <int L>
+PH_HD R<L> r_div(R<L> a, R<L> b)
+{
+    if constexpr (L == 1) {
+        return R<1>{{a.v[0] / b.v[0]}};
+    } else {
+        R<L> y = r_recip<L>(b);
+        R<L> q = r_mul<L>(a, y);
+        R<L> e = r_sub<L>(a, r_mul<L>(b, q));
+        return r_add<L>(q, r_mul<L>(y, e));
+    }
+}
+
+// sqrt(a), a >= 0: 1/sqrt(a) by Newton y <- y + y (1 - a y^2) / 2 from the
+// FP64 seed, then s = a y corrected once by s + y (a - s^2) / 2.
+template <int L>
+PH_HD R<L> r_sqrt(R<L> a)
+{
+    if (!(a.v[0] > 0.0)) return r_zero<L>();
+    if constexpr (L == 1) {
+        return R<1>{{sqrt(a.v[0])}};
+    } else {
+        R<L> y = r_from<L>(1.0 / sqrt(a.v[0]));
+        const int steps = L == 2 ? 1 : 2;
+        for (int s = 0; s < steps; ++s) {
+            R<L> e = r_sub<L>(r_from<L>(1.0), r_mul<L>(a, r_mul<L>(y, y)));
+            y = r_add<L>(y, r_mul_d<L>(r_mul<L>(y, e), 0.5));
+        }
+        R<L> sq = r_mul<L>(a, y);
+        R<L> e = r_sub<L>(a, r_mul<L>(sq, sq));
+        return r_add<L>(sq, r_mul_d<L>(r_mul<L>(y, e), 0.5));
+    }
+}
+
+// conj(a) * b
+template <int L>
+PH_HD C<L> c_cmul(C<L> a, C<L> b)
+{
+    a.im = r_neg<L>(a.im);
+    return c_mul<L>(a, b);
+}
+
+// |a|^2 as an L-limb real
+template <int L>
+PH_HD R<L> c_abs2(C<L> a)
+{
+    return r_add<L>(r_mul<L>(a.re, a.re), r_mul<L>(a.im, a.im));
+}
+
+// a + b with b an FP64 complex (the mixed-precision Newton update)
+template <int L>
+PH_HD C<L> c_add_c64(C<L> a, double br, double bi)
+{
+    C<L> b = c_from<L>(br, bi);
+    return c_add<L>(a, b);
+}
+
+// Generic names used by the term sweep.
+template <int L>
+PH_HD C<L> num_mul(C<L> a, C<L> b)
+{
+    return c_mul<L>(a, b);
+}
+
+template <int L>
+PH_HD C<L> num_scale(C<L> a, double s)
+{
+    return c_mul_d<L>(a, s);
+}
+
 // Leading limb (the FP64 value handed to the FP64 corrector).
 template <int L>
 PH_HD double r_hi(R<L> a)

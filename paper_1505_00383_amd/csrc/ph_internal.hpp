@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/ph.h"
+#include "ph_sweep.hpp"
 
 namespace ph {
 
@@ -26,12 +27,6 @@ int hip_fail(hipError_t e, const char *what);
         if (e_ != hipSuccess) return ph::hip_fail(e_, #call); \
     } while (0)
 
-// Factor word of the term tables: variable in bits 0..15, exponent in bits
-// 16..30, bit 31 set when this factor is the first contribution of its
-// equation to that Jacobian column (the kernel then stores instead of adding).
-constexpr uint32_t FAC_FIRST = 0x80000000u;
-__host__ __device__ inline int fac_var(uint32_t w) { return int(w & 0xffffu); }
-__host__ __device__ inline int fac_exp(uint32_t w) { return int((w >> 16) & 0x7fffu); }
 
 // Term descriptor: {k = number of factors, offset of the first factor word,
 // sel = 0 for a target term (coefficient scaled by t) or 1 for a start-system
