@@ -103,6 +103,67 @@ def time_eval(ph, torch, S, sysm, L, npts, steps, warmup, gamma):
     return ms, ok, x, t
 
 
+def time_track(ph, torch, sysm, L, mixed, npaths, reps=1):
+    """paths/s of ph_track on the first npaths start solutions (roots of unity)."""
+    from paper_1505_00383_amd import synth
+    S = ph.System(sysm)
+    g = synth.gamma_of(sysm)
+    opts = ph.track_opts(prec=L, mixed=mixed)
+    ph.track(S, g, min(npaths, 64), opts)          # warm-up (module load, caches)
+    st = torch.cuda.current_stream()
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        res = ph.track(S, g, npaths, opts)
+        e1.record(st)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3
+        if best is None or sec < best[0]:
+            best = (sec, res)
+    sec, res = best
+    rep = res["report"]
+    return {"paths": npaths, "seconds": sec, "paths_per_s": npaths / sec,
+            "success": int(rep["n_success"]), "failed_by_reason": {
+                k: int(rep[k]) for k in ("n_diverged", "n_step_underflow", "n_max_steps",
+                                         "n_singular", "n_nan")},
+            "steps_per_path": rep["steps"] / max(npaths, 1),
+            "newton_per_path": rep["newton_its"] / max(npaths, 1)}, res
+
+
+def endpoint_agreement(ph, a, b, n, L, npaths, tol):
+    xa = ph.from_soa(a["x_end"], npaths, (n, 2, L)).sum(-1)
+    xb = ph.from_soa(b["x_end"], npaths, (n, 2, L)).sum(-1)
+    ok = (a["status"] == 1) & (b["status"] == 1)
+    d = np.abs(xa - xb).max(-1).max(-1) / np.maximum(1.0, np.abs(xb).max(-1).max(-1))
+    return float(np.mean(ok & (d <= tol)))
+
+
+def tracking_extras(ph, torch):
+    from paper_1505_00383_amd import synth
+    out = {}
+    cub = synth.tracking_cubic()
+    B = 3 ** 8
+    dd_m, r_m = time_track(ph, torch, cub, 2, 1, B, reps=2)
+    dd_p, r_p = time_track(ph, torch, cub, 2, 0, B, reps=2)
+    d_p, _ = time_track(ph, torch, cub, 1, 0, B, reps=2)
+    out["track_n8_d3_6561paths"] = {
+        "double_plain": d_p, "dd_mixed": dd_m, "dd_plain": dd_p,
+        "dd_mixed_over_plain": dd_m["paths_per_s"] / dd_p["paths_per_s"],
+        "dd_endpoint_agreement_1e-24": endpoint_agreement(ph, r_m, r_p, 8, 2, B, 1e-24)}
+    q16 = synth.tracking_quadratic16()
+    sub = 4096
+    qd_m, q_m = time_track(ph, torch, q16, 4, 1, sub)
+    qd_p, q_p = time_track(ph, torch, q16, 4, 0, sub)
+    out["track_n16_d2_qd_4096paths"] = {
+        "qd_mixed": qd_m, "qd_plain": qd_p,
+        "qd_mixed_over_plain": qd_m["paths_per_s"] / qd_p["paths_per_s"],
+        "qd_endpoint_agreement_1e-48": endpoint_agreement(ph, q_m, q_p, 16, 4, sub, 1e-48)}
+    full, _ = time_track(ph, torch, q16, 4, 1, 2 ** 16)
+    out["track_n16_d2_qd_mixed_65536paths"] = full
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,7 +215,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
-                     "kernel": f"eval_kernel<{L},8,true,true>",
+                     "kernel": "eval_d_fast_kernel" if L == 1 else f"eval_kernel<{L},8,true,true>",
                      "flops_per_point": fpp, "bytes_per_point": bpp,
                      "hbm_GBps_compulsory": bpp * npts / secs / 1e9,
                      "hbm_frac_compulsory": bpp * npts / secs / PEAK_HBM},
@@ -170,6 +231,7 @@ def main():
             extras[f"eval_prec{L2}"] = {"points_per_s": npts / (ms2 * 1e-3), "ms": ms2,
                                         "fp64_frac": f2 * npts / (ms2 * 1e-3) / PEAK_FP64,
                                         "finite": ok2}
+        extras.update(tracking_extras(ph, torch))
         result["extras"] = extras
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(sysm, L, x, t, gamma)

@@ -26,6 +26,8 @@
 // bare variable product, as counted in Table 6).
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "ph_arith.hpp"
 #include "ph_internal.hpp"
 #include "ph_sweep.hpp"
@@ -106,7 +108,7 @@ __global__ void __launch_bounds__(512) eval_kernel(EvalArgs a)
 {
     extern __shared__ double xl[];
     const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int W = blockDim.x >> 6;
     const int64_t p = (int64_t)blockIdx.x * 64 + lane;
     const bool act = p < a.npts;
@@ -160,7 +162,7 @@ __global__ void __launch_bounds__(512) eval_kernel(EvalArgs a)
 #pragma unroll
             for (int l = 0; l < KMAX; ++l)
                 if (l < k) fw[l] = a.fac[d.y + l];
-            const C<L> tv_term = term_sweep<KMAX, JAC>(
+            const C<L> tv_term = term_sweep<KMAX, JAC, (L < 4)>(
                 k, fw, c, X, [&](int, uint32_t w, const C<L> &part) {
                     if constexpr (JAC)
                         jac_acc<L>(jrow0 + (int64_t)fac_var(w) * 2 * L * a.ld, a.ld,
@@ -179,6 +181,239 @@ __global__ void __launch_bounds__(512) eval_kernel(EvalArgs a)
                     double *jr = jrow0 + (int64_t)a.zc[z] * 2 * L * a.ld;
 #pragma unroll
                     for (int l = 0; l < 2 * L; ++l) jr[(int64_t)l * a.ld] = 0.0;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Complex double with n_var <= 32: the Jacobian row of the equation in flight
+// stays in registers.  The row is four 32-entry planes (low/high 32 bits of
+// the real and imaginary parts) so that a wave-uniform column index addresses
+// it through the GPR indexing mode (s_set_gpr_idx_on) without any branch:
+// four indexed moves in, two adds, four indexed moves out per partial.
+// ---------------------------------------------------------------------------
+typedef unsigned int v32u __attribute__((ext_vector_type(32)));
+
+struct RegRow {
+    v32u rl, rh, il, ih;
+};
+
+__device__ __forceinline__ void regrow_add(RegRow &r, int j, const C<1> &d)
+{
+    const unsigned long long a = ((unsigned long long)r.rh[j] << 32) | r.rl[j];
+    const unsigned long long b = ((unsigned long long)r.ih[j] << 32) | r.il[j];
+    const double x = __builtin_bit_cast(double, a) + d.re.v[0];
+    const double y = __builtin_bit_cast(double, b) + d.im.v[0];
+    const unsigned long long xa = __builtin_bit_cast(unsigned long long, x);
+    const unsigned long long yb = __builtin_bit_cast(unsigned long long, y);
+    r.rl[j] = (unsigned)xa;
+    r.rh[j] = (unsigned)(xa >> 32);
+    r.il[j] = (unsigned)yb;
+    r.ih[j] = (unsigned)(yb >> 32);
+}
+
+template <int KMAX>
+__global__ void __launch_bounds__(512) eval_d_regrow_kernel(EvalArgs a)
+{
+    extern __shared__ double xl[];
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    const int W = blockDim.x >> 6;
+    const int64_t p = (int64_t)blockIdx.x * 64 + lane;
+    const bool act = p < a.npts;
+    const int nv = a.n_var;
+    const int rows = nv * 2;
+    for (int r = w; r < rows; r += W) xl[r * 64 + lane] = act ? a.x[(int64_t)r * a.ld + p] : 0.0;
+    __syncthreads();
+    auto X = [&](int var) -> C<1> { return load_x<1>(xl, var, lane); };
+
+    double tv = 1.0;
+    if (a.t) tv = act ? a.t[p] : 0.0;
+    C<1> gs = c_zero<1>();
+    if (a.t) gs = c_mul_d<1>(c_from<1>(a.gre, a.gim), 1.0 - tv);
+
+    for (int i = blockIdx.y * W + w; i < a.n_eq; i += a.eq_stride) {
+        RegRow row;
+        row.rl = 0;
+        row.rh = 0;
+        row.il = 0;
+        row.ih = 0;
+        C<1> v = c_zero<1>();
+        const int s0 = a.eq_off[i], s1 = a.eq_off[i + 1];
+        for (int s = s0; s < s1; ++s) {
+            const int4 d = a.tdesc[s];
+            const int k = d.x;
+            C<1> c = c_from<1>(a.coef[(int64_t)s * 8], a.coef[(int64_t)s * 8 + 4]);
+            c = d.z ? c_mul<1>(c, gs) : c_mul_d<1>(c, tv);
+            if (k == 0) {
+                v = c_add<1>(v, c);
+                continue;
+            }
+            uint32_t fw[KMAX];
+#pragma unroll
+            for (int l = 0; l < KMAX; ++l)
+                if (l < k) fw[l] = __builtin_amdgcn_readfirstlane(a.fac[d.y + l]);
+            v = c_add<1>(v, term_sweep<KMAX, true, false>(k, fw, c, X,
+                                                   [&](int, uint32_t wd, const C<1> &part) {
+                                                       regrow_add(row, fac_var(wd), part);
+                                                   }));
+        }
+        if (act) {
+            a.val[((int64_t)(i * 2 + 0)) * a.ld + p] = v.re.v[0];
+            a.val[((int64_t)(i * 2 + 1)) * a.ld + p] = v.im.v[0];
+            double *jr = a.jac + (int64_t)i * nv * 2 * a.ld + p;
+#pragma unroll
+            for (int j = 0; j < 32; ++j) {
+                if (j < nv) {
+                    jr[(int64_t)(j * 2 + 0) * a.ld] =
+                        __builtin_bit_cast(double, ((unsigned long long)row.rh[j] << 32) | row.rl[j]);
+                    jr[(int64_t)(j * 2 + 1) * a.ld] =
+                        __builtin_bit_cast(double, ((unsigned long long)row.ih[j] << 32) | row.il[j]);
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Complex-double fast path (terms with k <= 8 factors and exponents <= 4):
+// per-point powers x, x^2, x^3 and a row of ones are staged in LDS, so the
+// common factor is k branch-free products by x^(a_l - 1); each k has its own
+// fully unrolled sweep; the exponent a_l rides in the FMA that adds the
+// partial into the register-resident Jacobian row; the total-degree start
+// part gamma (1-t) (x_i^d - 1) is evaluated once per equation by binary
+// powering.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ C<1> ldsc(const char *__restrict__ xb, uint32_t off, int lane)
+{
+    const double *p = reinterpret_cast<const double *>(xb + off);
+    return c_from<1>(p[lane], p[64 + lane]);
+}
+
+__device__ __forceinline__ void regrow_fma(RegRow &r, int j, double e, const C<1> &d)
+{
+    const unsigned long long a = ((unsigned long long)r.rh[j] << 32) | r.rl[j];
+    const unsigned long long b = ((unsigned long long)r.ih[j] << 32) | r.il[j];
+    const double x = __builtin_fma(e, d.re.v[0], __builtin_bit_cast(double, a));
+    const double y = __builtin_fma(e, d.im.v[0], __builtin_bit_cast(double, b));
+    const unsigned long long xa = __builtin_bit_cast(unsigned long long, x);
+    const unsigned long long yb = __builtin_bit_cast(unsigned long long, y);
+    r.rl[j] = (unsigned)xa;
+    r.rh[j] = (unsigned)(xa >> 32);
+    r.il[j] = (unsigned)yb;
+    r.ih[j] = (unsigned)(yb >> 32);
+}
+
+template <int K>
+__device__ __forceinline__ void dfast_sweep(const DTerm *__restrict__ r, const char *__restrict__ xb,
+                                            int lane, C<1> cf, RegRow &row, C<1> &v)
+{
+    C<1> xv[K];
+    C<1> q[K];
+#pragma unroll
+    for (int l = 0; l < K; ++l) {
+        xv[l] = ldsc(xb, r->xoff[l], lane);
+        cf = c_mul<1>(cf, ldsc(xb, r->poff[l], lane));
+    }
+    q[0] = cf;
+#pragma unroll
+    for (int l = 1; l < K; ++l) q[l] = c_mul<1>(q[l - 1], xv[l - 1]);
+    v = c_add<1>(v, c_mul<1>(q[K - 1], xv[K - 1]));
+    C<1> sfx = xv[K - 1];
+    regrow_fma(row, (int)r->var[K - 1], r->a[K - 1], q[K - 1]);
+#pragma unroll
+    for (int l = K - 2; l >= 0; --l) {
+        regrow_fma(row, (int)r->var[l], r->a[l], c_mul<1>(q[l], sfx));
+        if (l > 0) sfx = c_mul<1>(sfx, xv[l]);
+    }
+}
+
+__global__ void __launch_bounds__(512) eval_d_fast_kernel(EvalArgs a, const int32_t *__restrict__ d_run,
+                                                          const DTerm *__restrict__ dterm,
+                                                          const int32_t *__restrict__ d_deg, int planes)
+{
+    extern __shared__ double xl[];
+    const char *xb = reinterpret_cast<const char *>(xl);
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int W = blockDim.x >> 6;
+    const int64_t p = (int64_t)blockIdx.x * 64 + lane;
+    const bool act = p < a.npts;
+    const int nv = a.n_var;
+    // stage x and its powers: plane q holds x^(q+1)
+    for (int var = w; var < nv; var += W) {
+        C<1> x1 = act ? c_from<1>(a.x[(int64_t)(var * 2) * a.ld + p], a.x[(int64_t)(var * 2 + 1) * a.ld + p])
+                      : c_zero<1>();
+        C<1> z = x1;
+        for (int q = 0; q < planes; ++q) {
+            xl[((q * nv + var) * 2) * 64 + lane] = z.re.v[0];
+            xl[((q * nv + var) * 2 + 1) * 64 + lane] = z.im.v[0];
+            z = c_mul<1>(z, x1);
+        }
+    }
+    if (w == 0) {
+        xl[(planes * nv * 2) * 64 + lane] = 1.0;
+        xl[(planes * nv * 2 + 1) * 64 + lane] = 0.0;
+    }
+    __syncthreads();
+
+    double tv = 1.0;
+    if (a.t) tv = act ? a.t[p] : 0.0;
+    C<1> gs = c_zero<1>();
+    if (a.t) gs = c_mul_d<1>(c_from<1>(a.gre, a.gim), 1.0 - tv);
+
+    for (int i = blockIdx.y * W + w; i < a.n_eq; i += a.eq_stride) {
+        RegRow row;
+        row.rl = 0;
+        row.rh = 0;
+        row.il = 0;
+        row.ih = 0;
+        C<1> v = c_zero<1>();
+        const int32_t *run = d_run + i * 10;
+        auto coef = [&](const DTerm *r) -> C<1> {
+            const C<1> c = c_from<1>(r->cre, r->cim);
+            return r->sel ? c_mul<1>(c, gs) : c_mul_d<1>(c, tv);
+        };
+        for (int s = run[0]; s < run[1]; ++s) v = c_add<1>(v, coef(dterm + s));
+#define PH_DFAST_RUN(K)                                                        \
+        for (int s = run[K]; s < run[K + 1]; ++s) {                            \
+            const DTerm *r = dterm + s;                                        \
+            dfast_sweep<K>(r, xb, lane, coef(r), row, v);                      \
+        }
+        PH_DFAST_RUN(1)
+        PH_DFAST_RUN(2)
+        PH_DFAST_RUN(3)
+        PH_DFAST_RUN(4)
+        PH_DFAST_RUN(5)
+        PH_DFAST_RUN(6)
+        PH_DFAST_RUN(7)
+        PH_DFAST_RUN(8)
+#undef PH_DFAST_RUN
+        // total-degree start part: gamma (1-t) (x_i^d - 1), derivative d x_i^(d-1)
+        const int d = d_deg[i];
+        if (d > 0 && a.t) {
+            const C<1> xi = ldsc(xb, (uint32_t)(i * 2 * 64 * 8), lane);
+            C<1> pw = c_from<1>(1.0, 0.0), base = xi;  // pw = x_i^(d-1)
+            for (int e = d - 1; e > 0; e >>= 1) {
+                if (e & 1) pw = c_mul<1>(pw, base);
+                if (e > 1) base = c_mul<1>(base, base);
+            }
+            v = c_add<1>(v, c_mul<1>(gs, c_sub<1>(c_mul<1>(pw, xi), c_from<1>(1.0, 0.0))));
+            regrow_fma(row, i, (double)d, c_mul<1>(gs, pw));
+        }
+        if (act) {
+            a.val[((int64_t)(i * 2 + 0)) * a.ld + p] = v.re.v[0];
+            a.val[((int64_t)(i * 2 + 1)) * a.ld + p] = v.im.v[0];
+            double *jr = a.jac + (int64_t)i * nv * 2 * a.ld + p;
+#pragma unroll
+            for (int j = 0; j < 32; ++j) {
+                if (j < nv) {
+                    jr[(int64_t)(j * 2 + 0) * a.ld] =
+                        __builtin_bit_cast(double, ((unsigned long long)row.rh[j] << 32) | row.rl[j]);
+                    jr[(int64_t)(j * 2 + 1) * a.ld] =
+                        __builtin_bit_cast(double, ((unsigned long long)row.ih[j] << 32) | row.il[j]);
                 }
             }
         }
@@ -246,6 +481,35 @@ int eval_launch(const DevTable &tab, const double gamma[2], int prec, int64_t np
     const size_t lds = (size_t)tab.n_var * 2 * prec * 64 * sizeof(double);
     const bool xlds = lds <= 160 * 1024;
     const bool wj = jac != nullptr;
+    if (prec == 1 && wj && tab.n_var <= 32 && tab.dfast && !getenv("PH_EVAL_NO_DFAST")) {
+        const int Wr = tab.n_eq >= 8 ? 8 : W;
+        int Gr = 1;
+        while (blocks * Gr < 1024 && Gr * Wr * 2 <= tab.n_eq) Gr *= 2;
+        a.eq_stride = Gr * Wr;
+        const size_t ldsf = ((size_t)tab.dfast_planes * tab.n_var * 2 + 2) * 64 * sizeof(double);
+        dim3 grid((unsigned)blocks, (unsigned)Gr);
+        hipLaunchKernelGGL(eval_d_fast_kernel, grid, dim3(64 * Wr), ldsf, st, a, tab.d_run, tab.dterm,
+                           tab.d_deg, tab.dfast_planes);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "eval_d_fast_kernel launch");
+        return PH_OK;
+    }
+    if (prec == 1 && wj && tab.n_var <= 32 && tab.kmax <= 16 && !getenv("PH_EVAL_NO_REGROW")) {
+        const int Wr = tab.n_eq >= 8 ? 8 : W;
+        int Gr = 1;
+        while (blocks * Gr < 1024 && Gr * Wr * 2 <= tab.n_eq) Gr *= 2;
+        a.eq_stride = Gr * Wr;
+        dim3 grid((unsigned)blocks, (unsigned)Gr);
+        if (tab.kmax <= 4)
+            hipLaunchKernelGGL(eval_d_regrow_kernel<4>, grid, dim3(64 * Wr), lds, st, a);
+        else if (tab.kmax <= 8)
+            hipLaunchKernelGGL(eval_d_regrow_kernel<8>, grid, dim3(64 * Wr), lds, st, a);
+        else
+            hipLaunchKernelGGL(eval_d_regrow_kernel<16>, grid, dim3(64 * Wr), lds, st, a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return hip_fail(e, "eval_d_regrow_kernel launch");
+        return PH_OK;
+    }
     switch (prec) {
     case 1: return launch2<1>(a, tab.kmax, xlds, wj, W, G, lds, st);
     case 2: return launch2<2>(a, tab.kmax, xlds, wj, W, G, lds, st);

@@ -36,8 +36,30 @@ int hip_fail(hipError_t e, const char *what);
 // equation by equation: the instruction stream that every lane of a wave runs
 // on its own point (Section 3: all threads of a block evaluate the same
 // monomial at different points).
+// Term record of the complex-double fast path: everything one term needs in
+// one 160-byte block read through scalar loads.  xoff/poff are LDS byte
+// offsets of x_{j_l} and of x_{j_l}^{a_l - 1} (a table of ones, x, x^2, x^3
+// staged per point), a[l] the exponent as a double (folded into the FMA that
+// accumulates the partial), var[l] packed two per word.
+struct DTerm {
+    double cre, cim;
+    int32_t k, sel, pad0, pad1;
+    uint32_t xoff[8];
+    uint32_t poff[8];
+    double a[8];
+    uint32_t var[8];
+};
+
 struct DevTable {
     int n_eq = 0, n_var = 0, kmax = 0;
+    int emax = 0;                // largest exponent of a target/start term
+    bool dfast = false;          // the fast-path records below are valid
+    int dfast_planes = 0;        // power planes staged in LDS (x, x^2, x^3)
+    int32_t *d_eq_off = nullptr; // [n_eq + 1] offsets into dterm
+    DTerm *dterm = nullptr;      // fast-path records (target terms, custom start terms)
+    int32_t *d_deg = nullptr;    // [n_eq] total-degree start exponents (0: explicit start)
+    int32_t *d_run = nullptr;    // [n_eq][10]: records of equation i with k factors are
+                                 // d_run[i*10+k] .. d_run[i*10+k+1]-1
     int64_t n_terms = 0, n_fac = 0;
     int32_t *eq_off = nullptr;   // [n_eq + 1]
     int4 *tdesc = nullptr;       // [n_terms]

@@ -34,32 +34,47 @@ PH_SW int fac_exp(uint32_t w) { return int((w >> 16) & 0x7fffu); }
 
 // X(var) loads a coordinate; P(l, word, partial) consumes the partial
 // derivative with respect to factor l (already scaled by its exponent).
-// Returns the value of the term.  k must be in 1..KMAX.
-template <int KMAX, bool JAC, class Num, class XF, class PF>
+// Returns the value of the term.  k must be in 1..KMAX.  With KEEPX = false
+// the coordinates are loaded again for the backward products instead of
+// being held (fewer registers for wide number types).
+template <int KMAX, bool JAC, bool KEEPX = true, class Num, class XF, class PF>
 PH_SW Num term_sweep(int k, const uint32_t *fw, Num c, XF &&X, PF &&P)
 {
-    Num xv[KMAX];
+    Num xv[KEEPX ? KMAX : 1];
+    auto xat = [&](int l) -> Num {
+        if constexpr (KEEPX)
+            return xv[l];
+        else
+            return X(fac_var(fw[l]));
+    };
     Num q[KMAX];
     Num cf = c;
 #pragma unroll
     for (int l = 0; l < KMAX; ++l) {
         if (l < k) {
-            xv[l] = X(fac_var(fw[l]));
+            const Num xl = X(fac_var(fw[l]));
+            if constexpr (KEEPX) xv[l] = xl;
             const int e = fac_exp(fw[l]);
-            for (int r = 1; r < e; ++r) cf = num_mul(cf, xv[l]);
+            for (int r = 1; r < e; ++r) cf = num_mul(cf, xl);
         }
     }
     q[0] = cf;
 #pragma unroll
     for (int l = 1; l < KMAX; ++l)
-        if (l < k) q[l] = num_mul(q[l - 1], xv[l - 1]);
-    Num last = q[0], xlast = xv[0];
+        if (l < k) q[l] = num_mul(q[l - 1], xat(l - 1));
+    // last forward product and last coordinate, selected with static indices
+    Num last = q[0];
+    Num xlast;
+    if constexpr (KEEPX) xlast = xv[0];
+    uint32_t wlast = fw[0];
 #pragma unroll
     for (int l = 1; l < KMAX; ++l)
         if (l == k - 1) {
             last = q[l];
-            xlast = xv[l];
+            wlast = fw[l];
+            if constexpr (KEEPX) xlast = xv[l];
         }
+    if constexpr (!KEEPX) xlast = X(fac_var(wlast));
     Num value = num_mul(last, xlast);
     if constexpr (JAC) {
         Num sfx = xlast;
@@ -67,7 +82,7 @@ PH_SW Num term_sweep(int k, const uint32_t *fw, Num c, XF &&X, PF &&P)
         for (int l = KMAX - 1; l >= 0; --l) {
             if (l < k) {
                 Num part = (l == k - 1) ? q[l] : num_mul(q[l], sfx);
-                if (l < k - 1 && l > 0) sfx = num_mul(sfx, xv[l]);
+                if (l < k - 1 && l > 0) sfx = num_mul(sfx, xat(l));
                 const int e = fac_exp(fw[l]);
                 if (e != 1) part = num_scale(part, (double)e);
                 P(l, fw[l], part);

@@ -106,6 +106,68 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
             if (!touched[j]) zc.push_back(j);
         zc_off[i + 1] = int32_t(zc.size());
     }
+    // ---- complex-double fast path: records for terms with k <= 8 and
+    // exponents <= 4 (target terms, and explicit start terms); the
+    // total-degree start part is evaluated analytically per equation ----
+    int emax = 0;
+    bool dfast = true;
+    auto scan = [&](const HostSystem &sy) {
+        for (int t = 0; t < sy.eq_term_off[sy.n_eq]; ++t) {
+            int a = sy.term_fac_off[t], b = sy.term_fac_off[t + 1];
+            if (b - a > 8) dfast = false;
+            for (int q = a; q < b; ++q) emax = std::max(emax, sy.fac_exp[q]);
+        }
+    };
+    scan(f);
+    if (g) scan(*g);
+    if (emax > 4) dfast = false;
+    const int planes = std::max(1, std::min(emax, 4) - 1);  // x, x^2, x^3 as needed
+    std::vector<DTerm> dterm;
+    std::vector<int32_t> d_eq_off(ne + 1, 0), d_deg(ne, 0), d_run(1, 0);
+    if (dfast) {
+        // LDS layout per workgroup (doubles, 64 lanes): plane p (x^(p+1)) of
+        // variable v, component c at ((p * nv + v) * 2 + c) * 64; then a row
+        // of ones (re) and zeros (im)
+        const uint32_t ones_off = uint32_t(planes * nv * 2 * 64 * 8);
+        auto emit_d = [&](const HostSystem &sy, int i, int sel) {
+            for (int t = sy.eq_term_off[i]; t < sy.eq_term_off[i + 1]; ++t) {
+                DTerm r;
+                std::memset(&r, 0, sizeof r);
+                r.cre = sy.coef[size_t(t) * 8];
+                r.cim = sy.coef[size_t(t) * 8 + 4];
+                int a = sy.term_fac_off[t], b = sy.term_fac_off[t + 1];
+                r.k = b - a;
+                r.sel = sel;
+                for (int q = a; q < b; ++q) {
+                    int l = q - a, v = sy.fac_var[q], e = sy.fac_exp[q];
+                    r.xoff[l] = uint32_t(v * 2 * 64 * 8);
+                    r.poff[l] = e == 1 ? ones_off : uint32_t(((e - 2) * nv + v) * 2 * 64 * 8);
+                    r.a[l] = double(e);
+                    r.var[l] = uint32_t(v);
+                }
+                dterm.push_back(r);
+            }
+        };
+        d_run.assign(size_t(ne) * 10, 0);
+        for (int i = 0; i < ne; ++i) {
+            const size_t first = dterm.size();
+            emit_d(f, i, 0);
+            if (g) emit_d(*g, i, 1);
+            // group the equation's terms by their number of factors so the
+            // kernel runs one loop per k (a stable sort keeps the term order)
+            std::stable_sort(dterm.begin() + first, dterm.end(),
+                             [](const DTerm &x, const DTerm &y) { return x.k < y.k; });
+            for (int kk = 0; kk <= 9; ++kk) {
+                size_t pos = first;
+                while (pos < dterm.size() && dterm[pos].k < kk) ++pos;
+                d_run[size_t(i) * 10 + kk] = int32_t(pos);
+            }
+            d_eq_off[i + 1] = int32_t(dterm.size());
+            d_deg[i] = (!g && ne == nv) ? f.deg[i] : 0;
+        }
+        if (dterm.empty()) dterm.push_back(DTerm{});
+    }
+
     if (tdesc.empty()) {  // keep every pointer valid
         tdesc.push_back(int4{0, 0, 0, 0});
         coef.resize(8, 0.0);
@@ -119,7 +181,11 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
     size_t o_cf = o_fac + align256(fac.size() * 4);
     size_t o_zo = o_cf + align256(coef.size() * 8);
     size_t o_zc = o_zo + align256(zc_off.size() * 4);
-    size_t total = o_zc + align256(zc.size() * 4);
+    size_t o_deo = o_zc + align256(zc.size() * 4);
+    size_t o_dt = o_deo + align256(d_eq_off.size() * 4);
+    size_t o_dd = o_dt + align256(dterm.size() * sizeof(DTerm));
+    size_t o_dr = o_dd + align256(d_deg.size() * 4);
+    size_t total = o_dr + align256(d_run.size() * 4);
     std::vector<char> host(total, 0);
     std::memcpy(host.data() + o_eq, eq_off.data(), eq_off.size() * 4);
     std::memcpy(host.data() + o_td, tdesc.data(), tdesc.size() * sizeof(int4));
@@ -127,6 +193,10 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
     std::memcpy(host.data() + o_cf, coef.data(), coef.size() * 8);
     std::memcpy(host.data() + o_zo, zc_off.data(), zc_off.size() * 4);
     std::memcpy(host.data() + o_zc, zc.data(), zc.size() * 4);
+    std::memcpy(host.data() + o_deo, d_eq_off.data(), d_eq_off.size() * 4);
+    if (!dterm.empty()) std::memcpy(host.data() + o_dt, dterm.data(), dterm.size() * sizeof(DTerm));
+    std::memcpy(host.data() + o_dd, d_deg.data(), d_deg.size() * 4);
+    std::memcpy(host.data() + o_dr, d_run.data(), d_run.size() * 4);
     char *dev = nullptr;
     PH_HIP(hipMalloc(&dev, total));
     hipError_t e = hipMemcpy(dev, host.data(), total, hipMemcpyHostToDevice);
@@ -146,6 +216,13 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
     out.coef = reinterpret_cast<double *>(dev + o_cf);
     out.zc_off = reinterpret_cast<int32_t *>(dev + o_zo);
     out.zc = reinterpret_cast<int32_t *>(dev + o_zc);
+    out.emax = emax;
+    out.dfast = dfast;
+    out.dfast_planes = planes;
+    out.d_eq_off = reinterpret_cast<int32_t *>(dev + o_deo);
+    out.dterm = reinterpret_cast<DTerm *>(dev + o_dt);
+    out.d_deg = reinterpret_cast<int32_t *>(dev + o_dd);
+    out.d_run = reinterpret_cast<int32_t *>(dev + o_dr);
     return PH_OK;
 }
 
