@@ -162,7 +162,7 @@ __global__ void __launch_bounds__(512) eval_kernel(EvalArgs a)
 #pragma unroll
             for (int l = 0; l < KMAX; ++l)
                 if (l < k) fw[l] = a.fac[d.y + l];
-            const C<L> tv_term = term_sweep<KMAX, JAC, (L < 4)>(
+            const C<L> tv_term = term_sweep<KMAX, JAC, (L == 1)>(
                 k, fw, c, X, [&](int, uint32_t w, const C<L> &part) {
                     if constexpr (JAC)
                         jac_acc<L>(jrow0 + (int64_t)fac_var(w) * 2 * L * a.ld, a.ld,
@@ -306,26 +306,55 @@ __device__ __forceinline__ void regrow_fma(RegRow &r, int j, double e, const C<1
     r.ih[j] = (unsigned)(yb >> 32);
 }
 
+// Scalar copy of the part of a record the sweep needs first.
+struct DHead {
+    double cre, cim;
+    int sel;
+    uint32_t w[8];
+};
+
 template <int K>
-__device__ __forceinline__ void dfast_sweep(const DTerm *__restrict__ r, const char *__restrict__ xb,
-                                            int lane, C<1> cf, RegRow &row, C<1> &v)
+__device__ __forceinline__ DHead dfast_head(const DTerm *__restrict__ r)
+{
+    DHead h;
+    h.cre = r->cre;
+    h.cim = r->cim;
+    h.sel = r->sel;
+#pragma unroll
+    for (int l = 0; l < K; ++l) h.w[l] = r->w[l];
+    return h;
+}
+
+// One term with exactly K factors.  The head of the NEXT record (same K run)
+// is fetched once the coordinates of this term are in registers, so its
+// scalar-load latency overlaps the backward products.
+template <int K>
+__device__ __forceinline__ void dfast_sweep(const DHead &h, const DTerm *__restrict__ r,
+                                            const DTerm *__restrict__ rnext, DHead &hnext,
+                                            const char *__restrict__ xb, int lane, C<1> cf,
+                                            RegRow &row, C<1> &v)
 {
     C<1> xv[K];
     C<1> q[K];
 #pragma unroll
     for (int l = 0; l < K; ++l) {
-        xv[l] = ldsc(xb, r->xoff[l], lane);
-        cf = c_mul<1>(cf, ldsc(xb, r->poff[l], lane));
+        const uint32_t wl = h.w[l];
+        xv[l] = ldsc(xb, (wl & 0xffffu) * 1024u, lane);
+        cf = c_mul<1>(cf, ldsc(xb, (wl >> 16) * 8u, lane));
     }
     q[0] = cf;
 #pragma unroll
     for (int l = 1; l < K; ++l) q[l] = c_mul<1>(q[l - 1], xv[l - 1]);
     v = c_add<1>(v, c_mul<1>(q[K - 1], xv[K - 1]));
+    hnext = dfast_head<K>(rnext);
+    double ae[K];
+#pragma unroll
+    for (int l = 0; l < K; ++l) ae[l] = r->a[l];
     C<1> sfx = xv[K - 1];
-    regrow_fma(row, (int)r->var[K - 1], r->a[K - 1], q[K - 1]);
+    regrow_fma(row, (int)(h.w[K - 1] & 0xffffu), ae[K - 1], q[K - 1]);
 #pragma unroll
     for (int l = K - 2; l >= 0; --l) {
-        regrow_fma(row, (int)r->var[l], r->a[l], c_mul<1>(q[l], sfx));
+        regrow_fma(row, (int)(h.w[l] & 0xffffu), ae[l], c_mul<1>(q[l], sfx));
         if (l > 0) sfx = c_mul<1>(sfx, xv[l]);
     }
 }
@@ -378,9 +407,17 @@ __global__ void __launch_bounds__(512) eval_d_fast_kernel(EvalArgs a, const int3
         };
         for (int s = run[0]; s < run[1]; ++s) v = c_add<1>(v, coef(dterm + s));
 #define PH_DFAST_RUN(K)                                                        \
-        for (int s = run[K]; s < run[K + 1]; ++s) {                            \
-            const DTerm *r = dterm + s;                                        \
-            dfast_sweep<K>(r, xb, lane, coef(r), row, v);                      \
+        if (run[K] < run[K + 1]) {                                             \
+            DHead h = dfast_head<K>(dterm + run[K]);                           \
+            for (int s = run[K]; s < run[K + 1]; ++s) {                        \
+                const DTerm *r = dterm + s;                                    \
+                const DTerm *rn = dterm + (s + 1 < run[K + 1] ? s + 1 : s);    \
+                const C<1> c0 = c_from<1>(h.cre, h.cim);                       \
+                const C<1> c = h.sel ? c_mul<1>(c0, gs) : c_mul_d<1>(c0, tv);  \
+                DHead hn;                                                      \
+                dfast_sweep<K>(h, r, rn, hn, xb, lane, c, row, v);             \
+                h = hn;                                                        \
+            }                                                                  \
         }
         PH_DFAST_RUN(1)
         PH_DFAST_RUN(2)
@@ -473,7 +510,12 @@ int eval_launch(const DevTable &tab, const double gamma[2], int prec, int64_t np
     a.n_var = tab.n_var;
     // waves per workgroup: each wave takes its own equations of the same 64
     // points; more equation groups when there are few point blocks
-    const int W = tab.n_eq >= 4 ? 4 : tab.n_eq;
+    // waves per workgroup: all share the 64 points staged in LDS; wide
+    // precisions need more waves per workgroup because their LDS footprint
+    // (n * L KB) limits the workgroups per CU
+    const int Wwant = prec == 1 ? 4 : 8;
+    int W = 1;
+    while (W * 2 <= Wwant && W * 2 <= tab.n_eq) W *= 2;
     const int64_t blocks = (npts + 63) / 64;
     int G = 1;
     while (blocks * G < 1024 && G * W * 2 <= tab.n_eq) G *= 2;

@@ -37,17 +37,16 @@ int hip_fail(hipError_t e, const char *what);
 // on its own point (Section 3: all threads of a block evaluate the same
 // monomial at different points).
 // Term record of the complex-double fast path: everything one term needs in
-// one 160-byte block read through scalar loads.  xoff/poff are LDS byte
-// offsets of x_{j_l} and of x_{j_l}^{a_l - 1} (a table of ones, x, x^2, x^3
-// staged per point), a[l] the exponent as a double (folded into the FMA that
-// accumulates the partial), var[l] packed two per word.
+// one 128-byte block read through scalar loads.  w[l] = variable (bits 0..15)
+// and LDS byte offset of x_{j_l}^{a_l - 1} divided by 8 (bits 16..31; powers
+// x, x^2, x^3 and a row of ones are staged per point), a[l] the exponent as a
+// double (folded into the FMA that accumulates the partial).
 struct DTerm {
     double cre, cim;
-    int32_t k, sel, pad0, pad1;
-    uint32_t xoff[8];
-    uint32_t poff[8];
+    int32_t k, sel;
+    uint32_t w[8];
+    int32_t pad[2];
     double a[8];
-    uint32_t var[8];
 };
 
 struct DevTable {

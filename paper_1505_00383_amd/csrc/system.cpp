@@ -140,10 +140,9 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
                 r.sel = sel;
                 for (int q = a; q < b; ++q) {
                     int l = q - a, v = sy.fac_var[q], e = sy.fac_exp[q];
-                    r.xoff[l] = uint32_t(v * 2 * 64 * 8);
-                    r.poff[l] = e == 1 ? ones_off : uint32_t(((e - 2) * nv + v) * 2 * 64 * 8);
+                    const uint32_t poff = e == 1 ? ones_off : uint32_t(((e - 2) * nv + v) * 2 * 64 * 8);
+                    r.w[l] = uint32_t(v) | ((poff / 8) << 16);
                     r.a[l] = double(e);
-                    r.var[l] = uint32_t(v);
                 }
                 dterm.push_back(r);
             }
