@@ -120,6 +120,33 @@ int ph_eval_jac(const ph_system *target, const ph_system *start, const double ga
                 double *val, double *jac, void *stream);
 
 /*
+ * ph_eval_set_config -- pin the kernel and tiling ph_eval_jac uses for
+ * (target, start, prec): kernel 0 automatic, 1 general (Jacobian row
+ * accumulated in the output), 2 register-resident row (double, n_var <= 32),
+ * 3 double fast path (n_var <= 32, <= 8 factors per term, exponents <= 4);
+ * waves = waves per workgroup sharing one 64-point tile (1..8, 0 default);
+ * groups = equation groups per tile (power of two, 0 default).  All zero
+ * clears the setting.  Host-only; PH_EINVAL on bad values.  A kernel that
+ * does not apply makes later ph_eval_jac calls fail with PH_EUNSUPPORTED.
+ */
+int ph_eval_set_config(ph_system *target, const ph_system *start, int32_t prec, int32_t kernel,
+                       int32_t waves, int32_t groups);
+
+/*
+ * ph_eval_autotune -- time every applicable (kernel, waves, groups) choice of
+ * ph_eval_jac on the caller's buffers (same arguments as ph_eval_jac; the
+ * outputs are overwritten with a valid result) and keep the fastest for
+ * (target, start, prec).  With the environment variable PH_AUTOTUNE_CACHE
+ * naming a file, the choice is appended there and found again by later
+ * processes (keyed by a fingerprint of the systems).  best_ms (nullable)
+ * receives the average time of the chosen configuration.  Synchronises the
+ * stream.  Errors as ph_eval_jac.
+ */
+int ph_eval_autotune(ph_system *target, const ph_system *start, const double gamma[2],
+                     int32_t prec, int64_t npts, const double *t, const double *x, int64_t ld,
+                     double *val, double *jac, void *stream, double *best_ms);
+
+/*
  * Options of the path tracker (Section 2; the paper gives no constants,
  * defaults from ph_track_opts_default):
  *   prec            residual precision PH_D / PH_DD / PH_QD
@@ -136,11 +163,22 @@ int ph_eval_jac(const ph_system *target, const ph_system *start, const double ga
  *   diverge_norm    ||x||_inf beyond this fails the path (1e8)
  *   polish_tol      polish target relative to max(1,||x||); < 0 selects 8 u_prec
  *   max_steps       predictor steps per path (100000)
+ *   schedule        PH_SCHED_PERSISTENT (one persistent kernel drains a device
+ *                   work queue) or PH_SCHED_GRAPH (a round kernel captured in
+ *                   a hipGraph and replayed; slot state stays in device memory
+ *                   and only the count of active waves crosses to the host,
+ *                   Section 2, Table 3)
+ *   rounds_per_launch   graph schedule: tracker rounds per kernel launch (8)
+ *   launches_per_sync   graph schedule: graph replays between reads of the count (8)
+ *   blocks_per_cu   workgroups per CU (0: the library's default, 8)
  */
+#define PH_SCHED_PERSISTENT 0
+#define PH_SCHED_GRAPH 1
 typedef struct {
     int32_t prec, mixed, predictor_order, max_newton, expand_after, polish_max;
     double h_init, h_min, h_max, shrink, expand, tol_dx, diverge_norm, polish_tol;
     int64_t max_steps;
+    int32_t schedule, rounds_per_launch, launches_per_sync, blocks_per_cu;
 } ph_track_opts;
 
 /* Counts filled by ph_track when a report pointer is given. */

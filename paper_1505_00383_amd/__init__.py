@@ -24,7 +24,11 @@ REASONS = {0: "NONE", 1: "SUCCESS", 2: "DIVERGED", 3: "STEP_UNDERFLOW", 4: "MAX_
            5: "SINGULAR", 6: "NAN"}
 EXPORTED = ["ph_system_create", "ph_system_destroy", "ph_system_info", "ph_system_degrees",
             "ph_start_solutions", "ph_eval_jac", "ph_track_opts_default", "ph_last_error",
-            "ph_arith_probe", "ph_track", "ph_track_batch"]
+            "ph_arith_probe", "ph_track", "ph_track_batch", "ph_eval_set_config",
+            "ph_eval_autotune"]
+
+# ph_eval_set_config kernels
+EVAL_AUTO, EVAL_GENERAL, EVAL_REGROW, EVAL_FAST = 0, 1, 2, 3
 
 
 class TrackOpts(ctypes.Structure):
@@ -36,7 +40,12 @@ class TrackOpts(ctypes.Structure):
                 ("h_max", ctypes.c_double), ("shrink", ctypes.c_double),
                 ("expand", ctypes.c_double), ("tol_dx", ctypes.c_double),
                 ("diverge_norm", ctypes.c_double), ("polish_tol", ctypes.c_double),
-                ("max_steps", ctypes.c_int64)]
+                ("max_steps", ctypes.c_int64), ("schedule", ctypes.c_int32),
+                ("rounds_per_launch", ctypes.c_int32), ("launches_per_sync", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32)]
+
+
+SCHED_PERSISTENT, SCHED_GRAPH = 0, 1
 
 
 class TrackReport(ctypes.Structure):
@@ -88,6 +97,8 @@ def load_library(path: str = LIB_PATH):
     L.ph_arith_probe.argtypes = [i32, i32, i64, P, P, P, P]
     L.ph_track.argtypes = [P, P, P, i64, P, i64, P, P, P, P, P, P, P]
     L.ph_track_batch.argtypes = [i32, P, P, P, P, P, P, i64, P, P, P, P, P]
+    L.ph_eval_set_config.argtypes = [P, P, i32, i32, i32, i32]
+    L.ph_eval_autotune.argtypes = [P, P, P, i32, i64, P, P, i64, P, P, P, P]
     for name in EXPORTED:
         fn = getattr(L, name)
         if name != "ph_last_error":
@@ -210,6 +221,33 @@ def eval_jac(sys: System, x_soa, npts: int, prec: int, t=None, gamma=1.0 + 0j, s
                             _ptr(t), _ptr(x_soa), ld, _ptr(val), _ptr(jac) if want_jac else None,
                             _stream(stream)))
     return val, (jac if want_jac else None)
+
+
+def eval_set_config(sys: System, prec: int, kernel: int = EVAL_AUTO, waves: int = 0,
+                    groups: int = 0, start: System | None = None):
+    """Pin ph_eval_jac's kernel and tiling for (sys, start, prec) (ph_eval_set_config);
+    all zero restores the automatic choice."""
+    _check(load_library().ph_eval_set_config(sys.handle, None if start is None else start.handle,
+                                             prec, kernel, waves, groups))
+
+
+def eval_autotune(sys: System, x_soa, npts: int, prec: int, t=None, gamma=1.0 + 0j,
+                  start=None, val=None, jac=None, stream=None) -> float:
+    """Time every applicable kernel/tiling of ph_eval_jac on these buffers and keep
+    the fastest for (sys, start, prec) (ph_eval_autotune).  Returns its ms."""
+    torch = _torch()
+    ld = x_soa.shape[1]
+    if val is None:
+        val = torch.empty((sys.n_eq * 2 * prec, ld), dtype=torch.float64, device=x_soa.device)
+    if jac is None:
+        jac = torch.empty((sys.n_eq * sys.n_var * 2 * prec, ld), dtype=torch.float64,
+                          device=x_soa.device)
+    g = (ctypes.c_double * 2)(complex(gamma).real, complex(gamma).imag)
+    ms = ctypes.c_double(0.0)
+    _check(load_library().ph_eval_autotune(sys.handle, None if start is None else start.handle, g,
+                                           prec, npts, _ptr(t), _ptr(x_soa), ld, _ptr(val),
+                                           _ptr(jac), _stream(stream), ctypes.byref(ms)))
+    return ms.value
 
 
 def start_solutions(sys: System, prec: int, first: int, npaths: int, out=None, stream=None):

@@ -26,7 +26,9 @@
 // bare variable product, as counted in Table 6).
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
 #include <cstdlib>
+#include <cstring>
 
 #include "ph_arith.hpp"
 #include "ph_internal.hpp"
@@ -489,7 +491,7 @@ static int launch2(const EvalArgs &a, int kmax, bool xlds, bool jac, int W, int 
 
 int eval_launch(const DevTable &tab, const double gamma[2], int prec, int64_t npts,
                 const double *t, const double *x, int64_t ld, double *val, double *jac,
-                hipStream_t st)
+                hipStream_t st, const EvalCfg *cfg)
 {
     EvalArgs a;
     a.eq_off = tab.eq_off;
@@ -508,50 +510,51 @@ int eval_launch(const DevTable &tab, const double gamma[2], int prec, int64_t np
     a.gim = gamma ? gamma[1] : 0.0;
     a.n_eq = tab.n_eq;
     a.n_var = tab.n_var;
-    // waves per workgroup: each wave takes its own equations of the same 64
-    // points; more equation groups when there are few point blocks
-    // waves per workgroup: all share the 64 points staged in LDS; wide
-    // precisions need more waves per workgroup because their LDS footprint
-    // (n * L KB) limits the workgroups per CU
-    const int Wwant = prec == 1 ? 4 : 8;
+    const bool wj = jac != nullptr;
+    // which kernel: the fast path when its records exist, else the register
+    // row in double, else the general kernel
+    const bool can_fast = prec == 1 && wj && tab.n_var <= 32 && tab.dfast;
+    const bool can_reg = prec == 1 && wj && tab.n_var <= 32 && tab.kmax <= 16;
+    int kernel = cfg ? cfg->kernel : 0;
+    if (kernel == 3 && !can_fast) return fail(PH_EUNSUPPORTED, "fast path not available for this system");
+    if (kernel == 2 && !can_reg) return fail(PH_EUNSUPPORTED, "register-row kernel not available");
+    if (kernel == 0) kernel = can_fast ? 3 : (can_reg ? 2 : 1);
+    // waves per workgroup: all of them share the 64 points staged in LDS and
+    // take their own equations; wide precisions want more waves per
+    // workgroup because their LDS tile (n * L KB) limits workgroups per CU
     int W = 1;
-    while (W * 2 <= Wwant && W * 2 <= tab.n_eq) W *= 2;
+    const int Wwant = (cfg && cfg->W > 0) ? cfg->W : (kernel >= 2 ? 8 : (prec == 1 ? 4 : 8));
+    while (W * 2 <= Wwant && W * 2 <= tab.n_eq && W * 2 <= 8) W *= 2;
     const int64_t blocks = (npts + 63) / 64;
     int G = 1;
-    while (blocks * G < 1024 && G * W * 2 <= tab.n_eq) G *= 2;
+    if (cfg && cfg->G > 0) {
+        while (G * 2 <= cfg->G && G * W * 2 <= tab.n_eq) G *= 2;
+    } else {
+        while (blocks * G < 1024 && G * W * 2 <= tab.n_eq) G *= 2;
+    }
     a.eq_stride = G * W;
+    dim3 grid((unsigned)blocks, (unsigned)G);
     const size_t lds = (size_t)tab.n_var * 2 * prec * 64 * sizeof(double);
-    const bool xlds = lds <= 160 * 1024;
-    const bool wj = jac != nullptr;
-    if (prec == 1 && wj && tab.n_var <= 32 && tab.dfast && !getenv("PH_EVAL_NO_DFAST")) {
-        const int Wr = tab.n_eq >= 8 ? 8 : W;
-        int Gr = 1;
-        while (blocks * Gr < 1024 && Gr * Wr * 2 <= tab.n_eq) Gr *= 2;
-        a.eq_stride = Gr * Wr;
+    if (kernel == 3) {
         const size_t ldsf = ((size_t)tab.dfast_planes * tab.n_var * 2 + 2) * 64 * sizeof(double);
-        dim3 grid((unsigned)blocks, (unsigned)Gr);
-        hipLaunchKernelGGL(eval_d_fast_kernel, grid, dim3(64 * Wr), ldsf, st, a, tab.d_run, tab.dterm,
+        hipLaunchKernelGGL(eval_d_fast_kernel, grid, dim3(64 * W), ldsf, st, a, tab.d_run, tab.dterm,
                            tab.d_deg, tab.dfast_planes);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "eval_d_fast_kernel launch");
         return PH_OK;
     }
-    if (prec == 1 && wj && tab.n_var <= 32 && tab.kmax <= 16 && !getenv("PH_EVAL_NO_REGROW")) {
-        const int Wr = tab.n_eq >= 8 ? 8 : W;
-        int Gr = 1;
-        while (blocks * Gr < 1024 && Gr * Wr * 2 <= tab.n_eq) Gr *= 2;
-        a.eq_stride = Gr * Wr;
-        dim3 grid((unsigned)blocks, (unsigned)Gr);
+    if (kernel == 2) {
         if (tab.kmax <= 4)
-            hipLaunchKernelGGL(eval_d_regrow_kernel<4>, grid, dim3(64 * Wr), lds, st, a);
+            hipLaunchKernelGGL(eval_d_regrow_kernel<4>, grid, dim3(64 * W), lds, st, a);
         else if (tab.kmax <= 8)
-            hipLaunchKernelGGL(eval_d_regrow_kernel<8>, grid, dim3(64 * Wr), lds, st, a);
+            hipLaunchKernelGGL(eval_d_regrow_kernel<8>, grid, dim3(64 * W), lds, st, a);
         else
-            hipLaunchKernelGGL(eval_d_regrow_kernel<16>, grid, dim3(64 * Wr), lds, st, a);
+            hipLaunchKernelGGL(eval_d_regrow_kernel<16>, grid, dim3(64 * W), lds, st, a);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return hip_fail(e, "eval_d_regrow_kernel launch");
         return PH_OK;
     }
+    const bool xlds = lds <= 160 * 1024;
     switch (prec) {
     case 1: return launch2<1>(a, tab.kmax, xlds, wj, W, G, lds, st);
     case 2: return launch2<2>(a, tab.kmax, xlds, wj, W, G, lds, st);
@@ -559,13 +562,9 @@ int eval_launch(const DevTable &tab, const double gamma[2], int prec, int64_t np
     }
 }
 
-}  // namespace ph
-
-using namespace ph;
-
-extern "C" int ph_eval_jac(const ph_system *target, const ph_system *start, const double gamma[2],
-                           int32_t prec, int64_t npts, const double *t, const double *x, int64_t ld,
-                           double *val, double *jac, void *stream)
+static int eval_check(const ph_system *target, const ph_system *start, const double gamma[2],
+                      int32_t prec, int64_t npts, const double *t, const double *x, int64_t ld,
+                      const double *val)
 {
     if (!target) return fail(PH_EINVAL, "null target system");
     if (prec != 1 && prec != 2 && prec != 4) return fail(PH_EINVAL, "prec must be 1, 2 or 4");
@@ -578,8 +577,137 @@ extern "C" int ph_eval_jac(const ph_system *target, const ph_system *start, cons
     if (!start && t && target->h.n_eq != target->h.n_var)
         return fail(PH_EINVAL, "the total-degree start system needs a square target");
     if (t && !gamma) return fail(PH_EINVAL, "gamma is null");
+    return PH_OK;
+}
+
+// Look up a tuned configuration: in the handle, else in the PH_AUTOTUNE_CACHE
+// file (lines "eval <target fp> <start fp> <prec> <kernel> <W> <G> <ms>").
+static bool eval_cfg_lookup(const ph_system *target, const ph_system *start, int prec, EvalCfg &out)
+{
+    ph_system *tg = const_cast<ph_system *>(target);
+    std::lock_guard<std::mutex> lk(tg->mu);
+    auto it = tg->eval_cfg.find({start, prec});
+    if (it != tg->eval_cfg.end()) {
+        out = it->second;
+        return true;
+    }
+    const char *path = std::getenv("PH_AUTOTUNE_CACHE");
+    if (!path) return false;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    const unsigned long long sfp = start ? start->h.fingerprint : 0ull;
+    unsigned long long a = 0, b = 0;
+    int p = 0, k = 0, w = 0, g = 0;
+    double ms = 0;
+    bool found = false;
+    char tag[16];
+    while (std::fscanf(f, "%15s %llx %llx %d %d %d %d %lf", tag, &a, &b, &p, &k, &w, &g, &ms) == 8) {
+        if (std::strcmp(tag, "eval") == 0 && a == target->h.fingerprint && b == sfp && p == prec) {
+            out.kernel = k;
+            out.W = w;
+            out.G = g;
+            found = true;  // the last entry wins
+        }
+    }
+    std::fclose(f);
+    if (found) tg->eval_cfg[{start, prec}] = out;
+    return found;
+}
+
+}  // namespace ph
+
+using namespace ph;
+
+extern "C" int ph_eval_jac(const ph_system *target, const ph_system *start, const double gamma[2],
+                           int32_t prec, int64_t npts, const double *t, const double *x, int64_t ld,
+                           double *val, double *jac, void *stream)
+{
+    int rc = eval_check(target, start, gamma, prec, npts, t, x, ld, val);
+    if (rc || npts == 0) return rc;
     const DevTable *tab = nullptr;
-    int rc = get_table(target, start, &tab);
+    rc = get_table(target, start, &tab);
     if (rc) return rc;
-    return eval_launch(*tab, gamma, prec, npts, t, x, ld, val, jac, (hipStream_t)stream);
+    EvalCfg cfg;
+    const bool tuned = eval_cfg_lookup(target, start, prec, cfg);
+    return eval_launch(*tab, gamma, prec, npts, t, x, ld, val, jac, (hipStream_t)stream,
+                       tuned ? &cfg : nullptr);
+}
+
+extern "C" int ph_eval_set_config(ph_system *target, const ph_system *start, int32_t prec,
+                                  int32_t kernel, int32_t waves, int32_t groups)
+{
+    if (!target) return fail(PH_EINVAL, "null target system");
+    if (prec != 1 && prec != 2 && prec != 4) return fail(PH_EINVAL, "prec must be 1, 2 or 4");
+    if (kernel < 0 || kernel > 3 || waves < 0 || waves > 8 || groups < 0)
+        return fail(PH_EINVAL, "kernel must be 0..3, waves 0..8, groups >= 0");
+    std::lock_guard<std::mutex> lk(target->mu);
+    if (kernel == 0 && waves == 0 && groups == 0)
+        target->eval_cfg.erase({start, prec});
+    else
+        target->eval_cfg[{start, prec}] = EvalCfg{kernel, waves, groups};
+    return PH_OK;
+}
+
+extern "C" int ph_eval_autotune(ph_system *target, const ph_system *start, const double gamma[2],
+                                int32_t prec, int64_t npts, const double *t, const double *x,
+                                int64_t ld, double *val, double *jac, void *stream,
+                                double *best_ms)
+{
+    int rc = eval_check(target, start, gamma, prec, npts, t, x, ld, val);
+    if (rc) return rc;
+    if (npts == 0) return fail(PH_EINVAL, "autotuning needs npts > 0");
+    const DevTable *tab = nullptr;
+    rc = get_table(target, start, &tab);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    PH_HIP(hipEventCreate(&e0));
+    PH_HIP(hipEventCreate(&e1));
+    EvalCfg best;
+    double best_t = 1e300;
+    const int kernels[3] = {3, 2, 1};
+    for (int kk : kernels) {
+        for (int W = 1; W <= 8; W *= 2) {
+            for (int G = 1; G <= 8; G *= 2) {
+                if (W * G > tab->n_eq) continue;
+                EvalCfg c{kk, W, G};
+                rc = eval_launch(*tab, gamma, prec, npts, t, x, ld, val, jac, st, &c);
+                if (rc == PH_EUNSUPPORTED) break;  // this kernel does not apply
+                if (rc) goto done;
+                (void)hipEventRecord(e0, st);
+                for (int r = 0; r < 3 && !rc; ++r) rc = eval_launch(*tab, gamma, prec, npts, t, x, ld, val, jac, st, &c);
+                (void)hipEventRecord(e1, st);
+                if (rc) goto done;
+                if (hipEventSynchronize(e1) != hipSuccess) {
+                    rc = fail(PH_EHIP, "autotune timing");
+                    goto done;
+                }
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (ms / 3.0 < best_t) {
+                    best_t = ms / 3.0;
+                    best = c;
+                }
+            }
+            if (rc == PH_EUNSUPPORTED) break;
+        }
+        rc = PH_OK;
+    }
+    {
+        std::lock_guard<std::mutex> lk(target->mu);
+        target->eval_cfg[{start, prec}] = best;
+    }
+    if (const char *path = std::getenv("PH_AUTOTUNE_CACHE")) {
+        if (FILE *f = std::fopen(path, "a")) {
+            std::fprintf(f, "eval %llx %llx %d %d %d %d %.6f\n", (unsigned long long)target->h.fingerprint,
+                         (unsigned long long)(start ? start->h.fingerprint : 0ull), prec, best.kernel,
+                         best.W, best.G, best_t);
+            std::fclose(f);
+        }
+    }
+    if (best_ms) *best_ms = best_t;
+done:
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }

@@ -69,7 +69,15 @@ struct DevTable {
     void *block = nullptr;       // single device allocation holding all of the above
 };
 
+// Kernel choice and tiling of one evaluation: kernel 0 automatic, 1 general
+// (Jacobian row accumulated in the output), 2 register row (double, n <= 32),
+// 3 double fast path; W waves per workgroup, G equation groups (0: default).
+struct EvalCfg {
+    int kernel = 0, W = 0, G = 0;
+};
+
 struct HostSystem {
+    uint64_t fingerprint = 0;  // FNV-1a of the defining arrays
     int n_eq = 0, n_var = 0, max_k = 0;
     std::vector<int32_t> eq_term_off, term_fac_off, fac_var, fac_exp, deg;
     std::vector<double> coef;  // [T][2][4]
@@ -84,6 +92,7 @@ struct ph_system {
     ph::DevTable total;  // target merged with the total-degree start system
     std::mutex mu;
     std::map<const ph_system *, ph::DevTable> with_start;  // custom start systems
+    std::map<std::pair<const ph_system *, int>, ph::EvalCfg> eval_cfg;  // (start, prec) -> config
     int device = 0;
 };
 
@@ -94,4 +103,8 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out);
 void free_table(DevTable &t);
 // Table for (target, start), built on first use and cached in the target.
 int get_table(const ph_system *target, const ph_system *start, const DevTable **out);
+// Evaluation launch with an explicit configuration (cfg == NULL: defaults).
+int eval_launch(const DevTable &tab, const double gamma[2], int prec, int64_t npts,
+                const double *t, const double *x, int64_t ld, double *val, double *jac,
+                hipStream_t st, const EvalCfg *cfg);
 }  // namespace ph

@@ -16,8 +16,9 @@ struct SysDesc {
     const uint32_t *fac;
     const double *coef;
     const int64_t *path_ids; // multi-index number of every tracked path, or NULL (0..npaths-1)
-    int64_t path_off;        // first global path index of this system
+    int64_t path_off;        // first global path index of this system (outputs)
     int64_t npaths;
+    int64_t qoff;            // first queue index of this system inside its class
     double gre, gim;         // gamma
     int32_t n;               // equations = unknowns
     int32_t kmax;
@@ -25,10 +26,21 @@ struct SysDesc {
     int64_t radix[64];       // mixed-radix place values prod_{l<i} deg[l]
 };
 
+// One lane-count class of a launch: systems sys_first..sys_end-1 of the
+// descriptor table, whose paths are handed out by their own queue to the
+// blocks below block_end (and at or above the previous class's block_end).
+struct TrackClass {
+    int np;
+    int sys_first, sys_end;
+    int block_end;
+    int64_t total;
+    unsigned long long *queue;
+};
+
 struct TrackArgs {
     const SysDesc *sys;
     int nsys;
-    int64_t total_paths;
+    TrackClass cls[4];
     const double *x_start;   // SoA start points (rows (i*2+c)*L+l) or NULL: roots of unity
     int64_t ld_start;
     double *x_end;
@@ -36,15 +48,19 @@ struct TrackArgs {
     int8_t *status;
     int8_t *reason;
     int32_t *steps;
-    int32_t *newton;
-    unsigned long long *queue;  // next path to hand out
     unsigned long long *stats;  // [0] steps [1] rejected [2] newton iterations [3 + reason] counts
+    unsigned int *active;       // round schedule: waves still active after a launch
+    void *state;                // round schedule: per-lane slot state
+    int rounds;                 // round schedule: rounds per launch
     ph_track_opts o;
     double polish_tol;
     double eps_sing;
 };
 
-int track_launch(const TrackArgs &a, int prec, int np, int kmax, int blocks, hipStream_t st);
-int track_max_blocks(int prec, int np, int kmax, int mixed, int *blocks);
+int track_launch(const TrackArgs &a, int prec, int kmax, int blocks, size_t lds, hipStream_t st);
+size_t track_lds_bytes(int prec, int mixed, int np_max);
+size_t slot_bytes(int prec);
+int slot_init_launch(int prec, void *state, int64_t nslots, hipStream_t st);
+int clear_counter_launch(unsigned int *c, hipStream_t st);
 
 }  // namespace ph

@@ -1,0 +1,577 @@
+// ph_track_dev.hpp -- device code of the path tracker (included by the
+// per-precision translation units track_l1.hip, track_l2.hip, track_l4.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "ph_arith.hpp"
+#include "ph_internal.hpp"
+#include "ph_sweep.hpp"
+#include "ph_track.hpp"
+
+namespace ph {
+
+template <int NP>
+__device__ __forceinline__ double gsum_d(double v)
+{
+#pragma unroll
+    for (int o = 1; o < NP; o <<= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <int NP>
+__device__ __forceinline__ double gmax_d(double v)
+{
+#pragma unroll
+    for (int o = 1; o < NP; o <<= 1) {
+        double u = __shfl_xor(v, o);
+        v = (v != v || u != u) ? (v + u) : fmax(v, u);  // NaN propagates
+    }
+    return v;
+}
+
+template <int NP, int L>
+__device__ __forceinline__ R<L> gsum_r(R<L> v)
+{
+#pragma unroll
+    for (int o = 1; o < NP; o <<= 1) {
+        R<L> u;
+#pragma unroll
+        for (int l = 0; l < L; ++l) u.v[l] = __shfl_xor(v.v[l], o);
+        v = r_add<L>(v, u);
+    }
+    return v;
+}
+
+template <int NP, int L>
+__device__ __forceinline__ C<L> gsum_c(C<L> v)
+{
+    return C<L>{gsum_r<NP, L>(v.re), gsum_r<NP, L>(v.im)};
+}
+
+template <int L>
+__device__ __forceinline__ C<L> shfl_c(C<L> v, int src)
+{
+    C<L> r;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        r.re.v[l] = __shfl(v.re.v[l], src);
+        r.im.v[l] = __shfl(v.im.v[l], src);
+    }
+    return r;
+}
+
+template <int L>
+__device__ __forceinline__ double c_absd(C<L> a)
+{
+    return hypot(a.re.v[0], a.im.v[0]);
+}
+
+template <int L>
+__device__ __forceinline__ bool c_bad(C<L> a)
+{
+    return !isfinite(a.re.v[0]) || !isfinite(a.im.v[0]);
+}
+
+// LDS element access: 2 * LS doubles per complex entry.
+template <int LS>
+__device__ __forceinline__ C<LS> lds_get(const double *p)
+{
+    C<LS> z;
+#pragma unroll
+    for (int l = 0; l < LS; ++l) {
+        z.re.v[l] = p[l];
+        z.im.v[l] = p[LS + l];
+    }
+    return z;
+}
+
+template <int LS>
+__device__ __forceinline__ void lds_put(double *p, C<LS> z)
+{
+#pragma unroll
+    for (int l = 0; l < LS; ++l) {
+        p[l] = z.re.v[l];
+        p[LS + l] = z.im.v[l];
+    }
+}
+
+template <int LS, int L>
+__device__ __forceinline__ C<LS> narrow(C<L> a)
+{
+    C<LS> r = c_zero<LS>();
+#pragma unroll
+    for (int l = 0; l < LS; ++l) {
+        r.re.v[l] = a.re.v[l];
+        r.im.v[l] = a.im.v[l];
+    }
+    return r;
+}
+
+template <int L, int LS>
+__device__ __forceinline__ C<L> widen_add(C<L> a, C<LS> d)
+{
+    if constexpr (LS == L) {
+        return c_add<L>(a, d);
+    } else {
+        return c_add_c64<L>(a, d.re.v[0], d.im.v[0]);
+    }
+}
+
+// Root of unity exp(2 pi i k / d) for d dividing 12, in L limbs.
+template <int L>
+__device__ C<L> root_of_unity(int d, int k, const R<L> &h3)
+{
+    const int a = ((12 / d) * (k % d)) % 12;
+    R<L> c = r_zero<L>(), s = r_zero<L>();
+    switch (a) {
+    case 0: c = r_from<L>(1.0); break;
+    case 2: c = r_from<L>(0.5); s = h3; break;
+    case 3: s = r_from<L>(1.0); break;
+    case 4: c = r_from<L>(-0.5); s = h3; break;
+    case 6: c = r_from<L>(-1.0); break;
+    case 8: c = r_from<L>(-0.5); s = r_neg<L>(h3); break;
+    case 9: s = r_from<L>(-1.0); break;
+    case 10: c = r_from<L>(0.5); s = r_neg<L>(h3); break;
+    default: break;
+    }
+    return C<L>{c, s};
+}
+
+template <int L>
+__device__ R<L> half_sqrt3_t()
+{
+    R<L> three = r_from<L>(3.0);
+    return r_mul_d<L>(r_sqrt<L>(three), 0.5);
+}
+
+enum : int { PH_EMPTY = 0, PH_STEP = 1, PH_CORRECT = 2, PH_POLISH = 3, PH_RETIRED = 4 };
+
+// Everything a lane carries from one round to the next.  The path-level
+// fields are identical in all lanes of a group; x, xp, xh are coordinate i.
+template <int L>
+struct Slot {
+    int phase, sidx, n, succ, it, have_prev, pit;
+    int32_t steps, rejected, newton;
+    int64_t gid;
+    double t, tp, t1, h, dprev;
+    C<L> x, xp, xh;
+};
+
+template <int L>
+__device__ __forceinline__ void slot_init(Slot<L> &s)
+{
+    s.phase = PH_EMPTY;
+    s.sidx = s.n = s.succ = s.it = s.have_prev = s.pit = 0;
+    s.steps = s.rejected = s.newton = 0;
+    s.gid = 0;
+    s.t = s.tp = s.t1 = s.h = s.dprev = 0.0;
+    s.x = s.xp = s.xh = c_zero<L>();
+}
+
+// Run at most max_rounds rounds of the tracker on the slots of this wave, or
+// until every slot is retired (the queue of the class is empty).  Returns
+// true when the wave is retired.
+template <int L, int NP, int KMAX, bool MIXED>
+__device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass &cl, Slot<L> &S, int max_rounds,
+                           double *__restrict__ xsh, double *__restrict__ wsh)
+{
+    constexpr int LS = MIXED ? 1 : L;
+    const int lane = threadIdx.x;
+    const int g = lane / NP;
+    const int i = lane % NP;
+    const int base = g * NP;
+    const ph_track_opts &o = a.o;
+    const R<L> h3 = half_sqrt3_t<L>();
+    // LDS views: xg = the group's current iterate, W(j, row) = entry of the
+    // augmented matrix [J | -H] (column j = NP holds -H)
+    double *xg = xsh + (size_t)g * NP * 2 * L;
+    auto W = [&](int j, int row) -> double * {
+        return wsh + (((size_t)g * (NP + 1) + j) * NP + row) * 2 * LS;
+    };
+
+    int phase = S.phase, sidx = S.sidx, n = S.n, succ = S.succ, it = S.it;
+    int have_prev = S.have_prev, pit = S.pit;
+    int32_t steps = S.steps, rejected = S.rejected, newton = S.newton;
+    int64_t gid = S.gid;
+    double t = S.t, tp = S.tp, t1 = S.t1, h = S.h, dprev = S.dprev;
+    C<L> x = S.x, xp = S.xp, xh = S.xh;
+
+    auto finish = [&](int reason) {
+        if (i < n) {
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                a.x_end[((int64_t)(i * 2 + 0) * L + l) * a.ld_end + gid] = x.re.v[l];
+                a.x_end[((int64_t)(i * 2 + 1) * L + l) * a.ld_end + gid] = x.im.v[l];
+            }
+        }
+        if (i == 0) {
+            a.status[gid] = reason == PH_R_SUCCESS ? 1 : -1;
+            if (a.reason) a.reason[gid] = (int8_t)reason;
+            if (a.steps) a.steps[gid] = steps;
+            atomicAdd(&a.stats[0], (unsigned long long)steps);
+            atomicAdd(&a.stats[1], (unsigned long long)rejected);
+            atomicAdd(&a.stats[2], (unsigned long long)newton);
+            atomicAdd(&a.stats[3 + reason], 1ull);
+        }
+        phase = PH_EMPTY;
+        n = 0;
+    };
+
+    bool retired = false;
+    for (int round = 0; round < max_rounds; ++round) {
+        // ---- refill: pop a path from the device queue of this class -------
+        if (phase == PH_EMPTY) {
+            unsigned long long id = 0;
+            if (i == 0) id = atomicAdd(cl.queue, 1ull);
+            id = __shfl(id, base);
+            if ((int64_t)id >= cl.total) {
+                phase = PH_RETIRED;
+                n = 0;
+            } else {
+                const int64_t q = (int64_t)id;
+                sidx = cl.sys_first;
+                while (sidx + 1 < cl.sys_end && a.sys[sidx + 1].qoff <= q) ++sidx;
+                const SysDesc &sd = a.sys[sidx];
+                n = sd.n;
+                const int64_t local = q - sd.qoff;
+                gid = sd.path_off + local;
+                const int64_t pid = sd.path_ids ? sd.path_ids[local] : local;
+                x = c_zero<L>();
+                if (i < n) {
+                    if (a.x_start) {
+#pragma unroll
+                        for (int l = 0; l < L; ++l) {
+                            x.re.v[l] = a.x_start[((int64_t)(i * 2 + 0) * L + l) * a.ld_start + gid];
+                            x.im.v[l] = a.x_start[((int64_t)(i * 2 + 1) * L + l) * a.ld_start + gid];
+                        }
+                    } else {
+                        const int d = sd.deg[i];
+                        const int k = (int)((pid / sd.radix[i]) % d);
+                        x = root_of_unity<L>(d, k, h3);
+                    }
+                }
+                xp = x;
+                xh = x;
+                t = tp = 0.0;
+                h = o.h_init;
+                succ = it = have_prev = pit = 0;
+                steps = rejected = newton = 0;
+                phase = PH_STEP;
+            }
+        }
+        const bool any_bad = gmax_d<NP>(c_bad<L>(x) ? 1.0 : 0.0) > 0.0;
+        if (phase == PH_STEP && steps == 0) {
+            if (o.h_min > o.h_init) finish(PH_R_STEP_UNDERFLOW);
+            else if (any_bad) finish(PH_R_NAN);
+        }
+        // ---- stop when every slot of the wave is retired ------------------
+        if (__all(phase == PH_RETIRED)) {
+            retired = true;
+            break;
+        }
+
+        // ---- predictor ----------------------------------------------------
+        if (phase == PH_STEP) {
+            if (steps >= o.max_steps) {
+                finish(PH_R_MAX_STEPS);
+            } else {
+                ++steps;
+                if (h > 1.0 - t) h = 1.0 - t;
+                t1 = t + h;
+                if (t1 >= 1.0 - 1e-15) t1 = 1.0;
+                if (have_prev) {
+                    const double r = (t1 - t) / (t - tp);
+                    xh = c_add<L>(x, c_mul_d<L>(c_sub<L>(x, xp), r));
+                } else {
+                    xh = x;
+                }
+                it = 0;
+                dprev = 0.0;
+                phase = PH_CORRECT;
+            }
+        }
+        const bool busy = phase == PH_CORRECT || phase == PH_POLISH;
+        const double tt = phase == PH_POLISH ? 1.0 : t1;
+        const SysDesc &sd = a.sys[sidx];
+
+        // ---- evaluate H and J at (xh, tt): lane i does equation i ----------
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            xg[i * 2 * L + l] = xh.re.v[l];
+            xg[i * 2 * L + L + l] = xh.im.v[l];
+        }
+#pragma unroll
+        for (int j = 0; j <= NP; ++j) lds_put<LS>(W(j, i), c_zero<LS>());
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        C<L> v = c_zero<L>();
+        if (busy && i < n) {
+            double o1, oe;
+            two_sum(1.0, -tt, o1, oe);
+            R<L> omt = r_zero<L>();
+            omt.v[0] = o1;
+            if constexpr (L > 1) omt.v[1] = oe;
+            const C<L> gs = c_mul_r<L>(c_from<L>(sd.gre, sd.gim), omt);
+            auto X = [&](int var) -> C<L> {
+                C<L> z;
+#pragma unroll
+                for (int l = 0; l < L; ++l) {
+                    z.re.v[l] = xg[var * 2 * L + l];
+                    z.im.v[l] = xg[var * 2 * L + L + l];
+                }
+                return z;
+            };
+            const int s0 = sd.eq_off[i], s1 = sd.eq_off[i + 1];
+            for (int s = s0; s < s1; ++s) {
+                const int4 d = sd.tdesc[s];
+                C<L> c;
+#pragma unroll
+                for (int l = 0; l < L; ++l) {
+                    c.re.v[l] = sd.coef[(int64_t)s * 8 + l];
+                    c.im.v[l] = sd.coef[(int64_t)s * 8 + 4 + l];
+                }
+                c = d.z ? c_mul<L>(c, gs) : c_mul_d<L>(c, tt);
+                if (d.x == 0) {
+                    v = c_add<L>(v, c);
+                    continue;
+                }
+                uint32_t fw[KMAX];
+#pragma unroll
+                for (int l = 0; l < KMAX; ++l)
+                    if (l < d.x) fw[l] = sd.fac[d.y + l];
+                v = c_add<L>(v, term_sweep<KMAX, true, (L == 1)>(
+                                    d.x, fw, c, X, [&](int, uint32_t w, const C<L> &part) {
+                                        double *e = W(fac_var(w), i);
+                                        lds_put<LS>(e, c_add<LS>(lds_get<LS>(e), narrow<LS, L>(part)));
+                                    }));
+            }
+            lds_put<LS>(W(NP, i), narrow<LS, L>(c_sub<L>(c_zero<L>(), v)));
+        }
+
+        // ---- correct: MGS least squares on [J | -H], row i in lane i ------
+        double fro = 0.0;
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            C<LS> w = lds_get<LS>(W(j, i));
+            fro += w.re.v[0] * w.re.v[0] + w.im.v[0] * w.im.v[0];
+        }
+        fro = sqrt(gsum_d<NP>(fro));
+        bool sing = false;
+        C<LS> acc = c_zero<LS>();  // r_{i,rhs}, then the back-substitution value
+        // the column loops address LDS only, so they stay rolled (code size)
+#pragma unroll 1
+        for (int k = 0; k < n; ++k) {
+            {  // group-uniform
+                C<LS> wk = lds_get<LS>(W(k, i));
+                R<LS> nr = gsum_r<NP, LS>(c_abs2<LS>(wk));
+                R<LS> rkk = r_sqrt<LS>(nr);
+                if (!(rkk.v[0] > a.eps_sing * fro)) sing = true;
+                if (sing) break;
+                {
+                    R<LS> inv = r_div<LS>(r_from<LS>(1.0), rkk);
+                    C<LS> q = c_mul_r<LS>(wk, inv);
+#pragma unroll 1
+                    for (int j = k + 1; j <= NP; ++j) {
+                        if (j == n && j < NP) j = NP;  // skip the padding columns
+                        {
+                            double *ej = W(j, i);
+                            C<LS> wj = lds_get<LS>(ej);
+                            C<LS> r = gsum_c<NP, LS>(c_cmul<LS>(q, wj));
+                            lds_put<LS>(ej, c_sub<LS>(wj, c_mul<LS>(r, q)));
+                            if (i == k && j == NP) acc = r;
+                            // column k is dead after step k: R(k, j) goes to row j of it
+                            if (j < NP && i == j) lds_put<LS>(W(k, j), r);
+                        }
+                    }
+                    if (i == k) lds_put<LS>(W(k, k), C<LS>{rkk, r_zero<LS>()});
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        // back substitution R dx = r_rhs, column oriented: lane i keeps acc_i
+        C<LS> dxi = c_zero<LS>();
+#pragma unroll 1
+        for (int k = n - 1; k >= 0; --k) {
+            if (!sing) {
+                C<LS> dk = c_zero<LS>();
+                if (i == k) {
+                    R<LS> rkk = lds_get<LS>(W(k, k)).re;
+                    R<LS> inv = r_div<LS>(r_from<LS>(1.0), rkk);
+                    dk = c_mul_r<LS>(acc, inv);
+                    dxi = dk;
+                }
+                dk = shfl_c<LS>(dk, base + k);
+                if (i < k) {
+                    C<LS> rik = lds_get<LS>(W(i, k));  // R(i, k), stored in column i, row k
+                    acc = c_sub<LS>(acc, c_mul<LS>(rik, dk));
+                }
+            }
+        }
+        if (i >= n || !busy) dxi = c_zero<LS>();
+
+        // ---- per-path decisions ------------------------------------------
+        if (phase == PH_CORRECT) {
+            ++newton;
+            bool accept = false, reject = false;
+            if (sing) {
+                reject = true;
+            } else {
+                xh = widen_add<L, LS>(xh, dxi);
+                const double dn = gmax_d<NP>(i < n ? c_absd<LS>(dxi) : 0.0);
+                const double xn = gmax_d<NP>(i < n ? c_absd<L>(xh) : 0.0);
+                if (dn != dn || xn != xn) {
+                    reject = true;
+                } else if (dn <= o.tol_dx * (xn > 1.0 ? xn : 1.0)) {
+                    accept = true;
+                } else if (it >= 1 && dn > dprev) {
+                    reject = true;
+                } else {
+                    dprev = dn;
+                    ++it;
+                    if (it >= o.max_newton) reject = true;
+                }
+            }
+            if (accept) {
+                tp = t;
+                xp = x;
+                have_prev = 1;
+                t = t1;
+                x = xh;
+                if (++succ >= o.expand_after) {
+                    h = h * o.expand;
+                    if (h > o.h_max) h = o.h_max;
+                    succ = 0;
+                }
+                phase = (t == 1.0) ? PH_POLISH : PH_STEP;
+                pit = 0;
+                dprev = INFINITY;
+            } else if (reject) {
+                ++rejected;
+                h *= o.shrink;
+                succ = 0;
+                phase = PH_STEP;
+                if (h < o.h_min) finish(sing ? PH_R_SINGULAR : PH_R_STEP_UNDERFLOW);
+            }
+            if (accept || reject) {
+                if (phase != PH_EMPTY) {
+                    const bool bad = gmax_d<NP>((i < n && c_bad<L>(x)) ? 1.0 : 0.0) > 0.0;
+                    const double xn = gmax_d<NP>(i < n ? c_absd<L>(x) : 0.0);
+                    if (bad) finish(PH_R_NAN);
+                    else if (xn > o.diverge_norm) finish(PH_R_DIVERGED);
+                }
+            }
+        } else if (phase == PH_POLISH) {
+            // Newton on f at t = 1 until the update meets polish_tol, stops
+            // halving, or polish_max steps were taken
+            bool done = false;
+            if (sing) {
+                done = true;
+            } else {
+                const double dn = gmax_d<NP>(i < n ? c_absd<LS>(dxi) : 0.0);
+                if (pit > 0 && !(dn < 0.5 * dprev)) {
+                    done = true;
+                } else {
+                    x = widen_add<L, LS>(x, dxi);
+                    ++newton;
+                    const double xn = gmax_d<NP>(i < n ? c_absd<L>(x) : 0.0);
+                    if (dn <= a.polish_tol * (xn > 1.0 ? xn : 1.0)) done = true;
+                    dprev = dn;
+                    ++pit;
+                    if (pit >= o.polish_max) done = true;
+                }
+            }
+            xh = x;
+            if (done) finish(PH_R_SUCCESS);
+        }
+    }
+    S.phase = phase;
+    S.sidx = sidx;
+    S.n = n;
+    S.succ = succ;
+    S.it = it;
+    S.have_prev = have_prev;
+    S.pit = pit;
+    S.steps = steps;
+    S.rejected = rejected;
+    S.newton = newton;
+    S.gid = gid;
+    S.t = t;
+    S.tp = tp;
+    S.t1 = t1;
+    S.h = h;
+    S.dprev = dprev;
+    S.x = x;
+    S.xp = xp;
+    S.xh = xh;
+    return retired;
+}
+
+// LDS of one wave for lane count NP: the iterate (64 lanes x 2L doubles) and
+// the augmented matrices (64/NP paths x (NP+1) columns x NP rows x 2LS).
+template <int L, int NP, bool MIXED>
+__host__ __device__ constexpr size_t track_lds_doubles()
+{
+    return 64 * 2 * L + (size_t)(64 / NP) * (NP + 1) * NP * 2 * (MIXED ? 1 : L);
+}
+
+// Dispatch a block to its lane-count class.  Classes with lane counts 4, 8,
+// 16, 32 own consecutive block ranges; each runs its own work queue.  NPMAX
+// is the largest class present, so smaller launches do not carry the code
+// (and the registers) of the n <= 32 class.
+template <int L, int KMAX, bool MIXED, int NPMAX>
+__device__ __forceinline__ bool run_class(const TrackArgs &a, Slot<L> &S, int max_rounds, double *lds)
+{
+    const int b = blockIdx.x;
+    int c = 0;
+    while (c < 3 && b >= a.cls[c].block_end) ++c;
+    const TrackClass &cl = a.cls[c];
+    double *xsh = lds;
+    double *wsh = lds + 64 * 2 * L;
+    if (cl.np == 4) return run_rounds<L, 4, KMAX, MIXED>(a, cl, S, max_rounds, xsh, wsh);
+    if (cl.np == 8 || NPMAX == 8) return run_rounds<L, 8, KMAX, MIXED>(a, cl, S, max_rounds, xsh, wsh);
+    if constexpr (NPMAX >= 16)
+        if (cl.np == 16 || NPMAX == 16) return run_rounds<L, 16, KMAX, MIXED>(a, cl, S, max_rounds, xsh, wsh);
+    if constexpr (NPMAX >= 32) return run_rounds<L, 32, KMAX, MIXED>(a, cl, S, max_rounds, xsh, wsh);
+    return true;
+}
+
+// One kernel for both schedules.  Persistent (a.state == NULL): every wave
+// runs until its class queue is empty.  Rounds (a.state != NULL): every
+// launch runs a.rounds rounds and keeps each lane's slot in device memory
+// between launches; the host replays a captured graph of {clear counter,
+// this kernel} and reads the number of waves still active.
+template <int L, int KMAX, bool MIXED, int NPMAX>
+__global__ void __launch_bounds__(64) track_kernel(TrackArgs a)
+{
+    extern __shared__ double lds[];
+    Slot<L> *st = a.state ? reinterpret_cast<Slot<L> *>(a.state) + (size_t)blockIdx.x * 64 + threadIdx.x
+                          : nullptr;
+    Slot<L> S;
+    if (st)
+        S = *st;
+    else
+        slot_init<L>(S);
+    if (__all(S.phase == PH_RETIRED)) return;
+    const bool retired = run_class<L, KMAX, MIXED, NPMAX>(a, S, st ? a.rounds : 0x7fffffff, lds);
+    if (st) {
+        *st = S;
+        if (!retired && threadIdx.x == 0) atomicAdd(a.active, 1u);
+    }
+}
+
+template <int L>
+__global__ void __launch_bounds__(256) slot_init_kernel(void *state, int64_t nslots)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nslots) return;
+    Slot<L> S;
+    slot_init<L>(S);
+    reinterpret_cast<Slot<L> *>(state)[k] = S;
+}
+
+
+}  // namespace ph

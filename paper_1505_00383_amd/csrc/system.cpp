@@ -320,6 +320,22 @@ extern "C" int ph_system_create(int32_t n_eq, int32_t n_var, const int32_t *eq_t
         }
         h.deg[i] = best;
     }
+    // FNV-1a fingerprint of the defining arrays (autotuning cache key)
+    uint64_t fp = 1469598103934665603ull;
+    auto mix = [&fp](const void *p, size_t nb) {
+        const unsigned char *b = (const unsigned char *)p;
+        for (size_t i = 0; i < nb; ++i) fp = (fp ^ b[i]) * 1099511628211ull;
+    };
+    mix(&n_eq, sizeof n_eq);
+    mix(&n_var, sizeof n_var);
+    mix(h.eq_term_off.data(), h.eq_term_off.size() * 4);
+    mix(h.term_fac_off.data(), h.term_fac_off.size() * 4);
+    if (F > 0) {
+        mix(h.fac_var.data(), h.fac_var.size() * 4);
+        mix(h.fac_exp.data(), h.fac_exp.size() * 4);
+    }
+    mix(h.coef.data(), h.coef.size() * 8);
+    h.fingerprint = fp;
     PH_HIP(hipGetDevice(&s->device));
     rc = build_table(h, nullptr, s->total);
     if (rc) return rc;
@@ -375,5 +391,9 @@ extern "C" int ph_track_opts_default(ph_track_opts *o)
     o->diverge_norm = 1e8;
     o->polish_tol = -1.0;
     o->max_steps = 100000;
+    o->schedule = PH_SCHED_PERSISTENT;
+    o->rounds_per_launch = 8;
+    o->launches_per_sync = 8;
+    o->blocks_per_cu = 0;
     return PH_OK;
 }

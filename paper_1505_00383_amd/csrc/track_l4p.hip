@@ -1,0 +1,32 @@
+// track_l4p.hip -- tracker kernels, 4-limb residuals, 4-limb solves.
+#include "ph_track_dev.hpp"
+
+namespace ph {
+
+template <int KMAX, int NPMAX>
+static int launch_k(const TrackArgs &a, int blocks, size_t lds, hipStream_t st)
+{
+    hipLaunchKernelGGL((track_kernel<4, KMAX, false, NPMAX>), dim3(blocks), dim3(64), lds, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "track kernel launch");
+    return PH_OK;
+}
+
+template <int NPMAX>
+static int launch_n(const TrackArgs &a, int kmax, int blocks, size_t lds, hipStream_t st)
+{
+    if (kmax <= 4) return launch_k<4, NPMAX>(a, blocks, lds, st);
+    return launch_k<8, NPMAX>(a, blocks, lds, st);
+}
+
+int track_launch_l4p(const TrackArgs &a, int kmax, int blocks, size_t lds, hipStream_t st)
+{
+    int npmax = 4;
+    for (int c = 0; c < 4; ++c)
+        if (a.cls[c].total > 0) npmax = a.cls[c].np;
+    if (npmax <= 8) return launch_n<8>(a, kmax, blocks, lds, st);
+    if (npmax <= 16) return launch_n<16>(a, kmax, blocks, lds, st);
+    return launch_n<32>(a, kmax, blocks, lds, st);
+}
+
+}  // namespace ph

@@ -41,12 +41,15 @@ def test_opts_default_host_only(lib):
                                                    "expand_after", "polish_max")] + \
                    [(n, ctypes.c_double) for n in ("h_init", "h_min", "h_max", "shrink", "expand",
                                                     "tol_dx", "diverge_norm", "polish_tol")] + \
-                   [("max_steps", ctypes.c_int64)]
+                   [("max_steps", ctypes.c_int64)] + \
+                   [(n, ctypes.c_int32) for n in ("schedule", "rounds_per_launch", "launches_per_sync",
+                                                   "blocks_per_cu")]
     o = Opts()
     assert lib.ph_track_opts_default(ctypes.byref(o)) == 0
     assert (o.prec, o.max_newton, o.expand_after, o.polish_max) == (1, 3, 3, 8)
     assert (o.h_init, o.h_min, o.h_max, o.shrink, o.expand) == (0.01, 1e-10, 0.1, 0.5, 1.5)
     assert (o.tol_dx, o.diverge_norm, o.max_steps) == (1e-8, 1e8, 100000)
+    assert (o.schedule, o.rounds_per_launch, o.launches_per_sync, o.blocks_per_cu) == (0, 8, 8, 0)
     assert lib.ph_track_opts_default(None) == -1
 
 
@@ -72,6 +75,9 @@ def test_validation_errors_before_any_device_call(lib):
                               one.ctypes.data, cf.ctypes.data, 3, ctypes.byref(h))
     assert rc == -1 and b"coef_limbs" in lib.ph_last_error()
     assert lib.ph_eval_jac(None, None, None, 1, 1, None, None, 1, None, None, None) == -1
+    assert lib.ph_eval_set_config(None, None, 1, 0, 0, 0) == -1
+    assert lib.ph_eval_autotune(None, None, None, 1, 1, None, None, 1, None, None, None,
+                                None) == -1
 
 
 def test_binding_fails_loudly_without_gpu(lib):

@@ -193,3 +193,46 @@ def test_batch_heterogeneous_small():
         ok = (sub["status"] == 1) & (ref["status"] == 1)
         assert ok.mean() >= 0.9
         assert np.all(_rel(xg[ok], ref["x"][ok]) <= 1e-8)
+
+
+def test_graph_schedule_matches_persistent_bitwise():
+    """The round kernel replayed from a captured hipGraph (slot state kept in
+    device memory between launches, only the active-wave count read back)
+    gives bitwise the same endpoints, status and step counts as the
+    persistent kernel."""
+    s = synth.tracking_cubic()
+    g = synth.gamma_of(s)
+    S = ph.System(s)
+    a = ph.track(S, g, 500, ph.track_opts(prec=2, mixed=1))
+    b = ph.track(S, g, 500, ph.track_opts(prec=2, mixed=1, schedule=ph.SCHED_GRAPH,
+                                          rounds_per_launch=5, launches_per_sync=3))
+    print(f"[gpu] graph schedule: persistent {a['report']['seconds']:.3f}s graph "
+          f"{b['report']['seconds']:.3f}s", flush=True)
+    assert np.array_equal(a["x_end"].cpu().numpy(), b["x_end"].cpu().numpy())
+    for k in ("status", "reason", "steps"):
+        assert np.array_equal(a[k], b[k])
+    assert a["report"]["newton_its"] == b["report"]["newton_its"]
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_batch_lane_classes(schedule):
+    """Systems of n = 3, 6, 12 (4, 8 and 16 lanes per path) in one launch."""
+    rng = np.random.default_rng(17)
+    systems, gammas, paths = [], [], []
+    for n, nt, npath in ((3, 5, 8), (6, 7, 40), (12, 6, 24), (5, 5, 32)):
+        eqs = [synth._equation_with_anchor(rng, list(range(n)), i, 2, nt) for i in range(n)]
+        systems.append(synth.system_from_terms(n, eqs))
+        gammas.append(synth.unit_complex(rng))
+        paths.append(np.sort(rng.choice(2 ** n, size=min(npath, 2 ** n), replace=False)))
+    res = ph.track_batch([ph.System(x) for x in systems], gammas, paths,
+                         ph.track_opts(prec=2, mixed=1, schedule=schedule, rounds_per_launch=16))
+    off = res["path_off"]
+    X = ph.from_soa(res["x_end"], int(off[-1]), (12, 2, 2))
+    for k, sy in enumerate(systems):
+        sl = slice(off[k], off[k + 1])
+        ref = oracle.track(sy, gammas[k], paths[k], oracle.Opts(prec=2), threads=THREADS)
+        ok = (res["status"][sl] == 1) & (ref["status"] == 1)
+        assert ok.mean() >= 0.9, (k, res["status"][sl], ref["status"])
+        rel = _rel(X[sl, :sy.n_var][ok], ref["x"][ok])
+        print(f"[gpu] class batch n={sy.n_var} paths={len(paths[k])} max_rel={rel.max():.1e}", flush=True)
+        assert np.all(rel <= 1e-8)

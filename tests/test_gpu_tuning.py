@@ -1,0 +1,118 @@
+"""Kernel choice, tiling and autotuning of ph_eval_jac: every configuration
+ph_eval_set_config accepts gives oracle-exact results, a kernel that does not
+apply is refused, and ph_eval_autotune's choice persists in its cache file
+(looked up by the systems' fingerprints)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1505_00383_amd as ph
+from paper_1505_00383_amd import synth
+from tests.parity import TOL, scaled_error
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _eval(S, s, L, x, t, gamma):
+    import torch
+    npts = x.shape[0]
+    xs = ph.to_soa(x)
+    tt = torch.as_tensor(np.ascontiguousarray(t), dtype=torch.float64).cuda()
+    val, jm = ph.eval_jac(S, xs, npts, L, tt, gamma)
+    torch.cuda.synchronize()
+    return (ph.from_soa(val, npts, (s.n_eq, 2, L)),
+            ph.from_soa(jm, npts, (s.n_eq, s.n_var, 2, L)))
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_every_configuration_matches_oracle(L):
+    s = synth.eval_dense(seed=778, n=16, terms_per_eq=10, k=5)
+    rng = np.random.default_rng(11)
+    npts = 64 * 3 + 29
+    x = synth.random_points(s.n_var, npts, L, rng, 0.95)
+    t = rng.uniform(0, 1, npts)
+    g = synth.gamma_of(s)
+    ov, oj, sv, sj = oracle.eval_homotopy(s, L, x, t, g)
+    S = ph.System(s)
+    kernels = [ph.EVAL_GENERAL] + ([ph.EVAL_REGROW, ph.EVAL_FAST] if L == 1 else [])
+    worst = 0.0
+    for k in kernels:
+        for W in (1, 2, 4, 8):
+            for G in (1, 2, 4):
+                ph.eval_set_config(S, L, k, W, G)
+                v, j = _eval(S, s, L, x, t, g)
+                e = max(scaled_error(v, ov, sv), scaled_error(j, oj, sj))
+                worst = max(worst, e)
+                assert e <= TOL[L], (k, W, G, e)
+    ph.eval_set_config(S, L)   # back to automatic
+    v, j = _eval(S, s, L, x, t, g)
+    assert max(scaled_error(v, ov, sv), scaled_error(j, oj, sj)) <= TOL[L]
+    print(f"[gpu] L={L} configs ok, worst err/S={worst:.2e}", flush=True)
+
+
+def test_inapplicable_kernel_is_refused():
+    s = synth.eval_dense(seed=779, n=6, terms_per_eq=5, k=4)
+    S = ph.System(s)
+    rng = np.random.default_rng(12)
+    x = synth.random_points(s.n_var, 70, 2, rng)
+    ph.eval_set_config(S, 2, ph.EVAL_FAST)            # double only
+    with pytest.raises(ph.PHError, match="-4"):
+        _eval(S, s, 2, x, rng.uniform(0, 1, 70), 1.0)
+    with pytest.raises(ph.PHError):
+        ph.eval_set_config(S, 1, 7)
+
+
+def test_autotune_choice_persists_in_cache_file(tmp_path, monkeypatch):
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("PH_AUTOTUNE_CACHE", str(cache))
+    import torch
+    s = synth.eval_dense(seed=780, n=8, terms_per_eq=20, k=4)
+    L = 1
+    rng = np.random.default_rng(13)
+    npts = 4096
+    x = synth.random_points(s.n_var, npts, L, rng, 0.95)
+    t = rng.uniform(0, 1, npts)
+    g = synth.gamma_of(s)
+    S = ph.System(s)
+    xs = ph.to_soa(x)
+    tt = torch.as_tensor(t, dtype=torch.float64).cuda()
+    ms = ph.eval_autotune(S, xs, npts, L, tt, g)
+    assert ms > 0
+    lines = cache.read_text().split("\n")
+    fields = lines[0].split()
+    assert fields[0] == "eval" and int(fields[3]) == L and int(fields[4]) in (1, 2, 3)
+    print(f"[gpu] autotune -> {lines[0]}", flush=True)
+    # the tuned configuration still gives oracle-exact results
+    idx = np.array([0, 1, 63, 64, 2000, npts - 1])
+    v, j = _eval(S, s, L, x, t, g)
+    ov, oj, sv, sj = oracle.eval_homotopy(s, L, x[idx], t[idx], g)
+    assert max(scaled_error(v[idx], ov, sv), scaled_error(j[idx], oj, sj)) <= TOL[L]
+    # a new handle of the same system finds the entry by fingerprint: pin the
+    # general kernel with one wave through the file and check it is taken
+    fields[4:7] = ["1", "1", "1"]
+    cache.write_text(" ".join(fields) + "\n")
+    S2 = ph.System(s)
+    v2, j2 = _eval(S2, s, L, x, t, g)
+    assert max(scaled_error(v2[idx], ov, sv), scaled_error(j2[idx], oj, sj)) <= TOL[L]
+    # and an entry asking for a kernel that cannot run is honoured (and refused)
+    s3 = synth.eval_dense(seed=781, n=6, terms_per_eq=5, k=4)
+    S3 = ph.System(s3)
+    x3 = synth.random_points(6, 64, 2, rng)
+    t3 = rng.uniform(0, 1, 64)
+    import torch as _t
+    ph.eval_autotune(S3, ph.to_soa(x3), 64, 2, _t.as_tensor(t3, dtype=_t.float64).cuda(), g)
+    last = cache.read_text().strip().split("\n")[-1].split()
+    assert int(last[3]) == 2 and int(last[4]) == 1      # only the general kernel runs DD
+    last[4] = "3"
+    cache.write_text(" ".join(last) + "\n")
+    with pytest.raises(ph.PHError, match="-4"):
+        _eval(ph.System(s3), s3, 2, x3, t3, g)
