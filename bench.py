@@ -81,9 +81,9 @@ def cpu_baseline(sysm, L, x, t, gamma, target_s=15.0):
                       f"over contiguous point ranges, {wall:.1f} s wall"}
 
 
-def time_eval(ph, torch, S, sysm, L, npts, steps, warmup, gamma):
+def time_eval(ph, torch, S, sysm, L, npts, steps, warmup, gamma, rng=None):
     from paper_1505_00383_amd import synth
-    x, t = synth.torus_points(sysm, npts, L)
+    x, t = synth.torus_points(sysm, npts, L, rng)
     xs = ph.to_soa(x)
     tt = torch.as_tensor(t, dtype=torch.float64).cuda()
     val = torch.empty((sysm.n_eq * 2 * L, npts), dtype=torch.float64, device="cuda")
@@ -139,9 +139,72 @@ def endpoint_agreement(ph, a, b, n, L, npaths, tol):
     return float(np.mean(ok & (d <= tol)))
 
 
+def time_batch(ph, torch, systems, gammas, paths, opts):
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    res = ph.track_batch(systems, gammas, paths, opts)
+    e1.record(st)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3
+    rep = res["report"]
+    total = int(res["path_off"][-1])
+    return {"paths": total, "seconds": sec, "paths_per_s": total / sec,
+            "success": int(rep["n_success"]), "failed_by_reason": {
+                k: int(rep[k]) for k in ("n_diverged", "n_step_underflow", "n_max_steps",
+                                         "n_singular", "n_nan")},
+            "steps_per_path": rep["steps"] / max(total, 1),
+            "newton_per_path": rep["newton_its"] / max(total, 1)}
+
+
+def batch_extra(ph, torch):
+    """64 systems, n ~ U{4..16}, d ~ U{2,3}, 8..32 terms per equation, about
+    200k paths in one launch, DD residual with FP64 Newton solves; the launch
+    shape is autotuned on a 16384-path sample, then the whole batch runs
+    under the graph schedule and the persistent schedule."""
+    from paper_1505_00383_amd import synth
+    sysms, gammas, paths, cap = synth.batch_heterogeneous()
+    systems = [ph.System(s) for s in sysms]
+    base = ph.track_opts(prec=2, mixed=1)
+    tuned, tsec = ph.track_autotune(systems, gammas, paths, base, sample=16384)
+    graph = ph.track_opts(prec=2, mixed=1, schedule=ph.SCHED_GRAPH,
+                          blocks_per_cu=tuned.blocks_per_cu,
+                          rounds_per_launch=tuned.rounds_per_launch)
+    out = {"systems": len(sysms), "cap": int(cap),
+           "n_hist": {int(n): int(sum(1 for s in sysms if s.n_var == n))
+                      for n in sorted({s.n_var for s in sysms})},
+           "tuned": {"schedule": "graph" if tuned.schedule == ph.SCHED_GRAPH else "persistent",
+                     "rounds_per_launch": tuned.rounds_per_launch,
+                     "blocks_per_cu": tuned.blocks_per_cu, "sample_seconds": tsec}}
+    out["tuned_run"] = time_batch(ph, torch, systems, gammas, paths, tuned)
+    out["graph"] = time_batch(ph, torch, systems, gammas, paths, graph)
+    out["persistent_default"] = time_batch(ph, torch, systems, gammas, paths, base)
+    return out
+
+
+def hbm_extra(ph, torch, steps):
+    """Double-precision eval of the n = 16, degree-2 tracking system (k <= 2)
+    at 2^20 points: about 1 flop per compulsory byte, so HBM-bound."""
+    from paper_1505_00383_amd import synth
+    s = synth.tracking_quadratic16()
+    npts = 1 << 20
+    S = ph.System(s)
+    rng = np.random.Generator(np.random.PCG64(synth.SEED_BASE + 3))
+    ms, ok, _, _ = time_eval(ph, torch, S, s, 1, npts, steps, 2, synth.gamma_of(s), rng)
+    bpp = bytes_per_point(s, 1)
+    fpp = flops_per_point(s, 1)
+    return {"points": npts, "ms": ms, "points_per_s": npts / (ms * 1e-3),
+            "bytes_per_point": bpp, "flops_per_point": fpp,
+            "hbm_GBps_compulsory": bpp * npts / (ms * 1e-3) / 1e9,
+            "hbm_frac_compulsory": bpp * npts / (ms * 1e-3) / PEAK_HBM, "finite": ok}
+
+
 def tracking_extras(ph, torch):
     from paper_1505_00383_amd import synth
     out = {}
+    small = synth.tracking_small()
+    d_small, _ = time_track(ph, torch, small, 1, 0, 8, reps=3)
+    out["track_n3_d2_8paths_double"] = d_small
     cub = synth.tracking_cubic()
     B = 3 ** 8
     dd_m, r_m = time_track(ph, torch, cub, 2, 1, B, reps=2)
@@ -174,9 +237,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: the many-path hot path shards paths across GPUs "
-              f"with no exchange until a final gather, and multi-GPU runs are not part of this "
-              f"build (asked for --gpus {args.gpus}).", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): paths and "
+              f"points shard across GPUs with no exchange until a final gather, which is a "
+              f"design here, not an implemented launcher.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -231,7 +294,9 @@ def main():
             extras[f"eval_prec{L2}"] = {"points_per_s": npts / (ms2 * 1e-3), "ms": ms2,
                                         "fp64_frac": f2 * npts / (ms2 * 1e-3) / PEAK_FP64,
                                         "finite": ok2}
+        extras["eval_n16_d2_hbm_1M_points_double"] = hbm_extra(ph, torch, max(3, args.steps // 4))
         extras.update(tracking_extras(ph, torch))
+        extras["track_batch64_dd_mixed"] = batch_extra(ph, torch)
         result["extras"] = extras
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(sysm, L, x, t, gamma)

@@ -35,7 +35,7 @@ extern "C" {
 #define PH_EINVAL (-1)       /* bad size, pointer, precision or exponent */
 #define PH_ENOMEM (-2)       /* device or host allocation failed */
 #define PH_EHIP (-3)         /* a HIP runtime call failed (message has the HIP error) */
-#define PH_EUNSUPPORTED (-4) /* valid request outside what this build handles */
+#define PH_EUNSUPPORTED (-4) /* valid request outside what the library handles */
 
 #define PH_D 1
 #define PH_DD 2
@@ -123,7 +123,8 @@ int ph_eval_jac(const ph_system *target, const ph_system *start, const double ga
  * ph_eval_set_config -- pin the kernel and tiling ph_eval_jac uses for
  * (target, start, prec): kernel 0 automatic, 1 general (Jacobian row
  * accumulated in the output), 2 register-resident row (double, n_var <= 32),
- * 3 double fast path (n_var <= 32, <= 8 factors per term, exponents <= 4);
+ * 3 double fast path (n_var <= 32, <= 8 factors per term, exponents <= 4)
+ * with the row in pinned registers, 4 the same with a compiler-held row;
  * waves = waves per workgroup sharing one 64-point tile (1..8, 0 default);
  * groups = equation groups per tile (power of two, 0 default).  All zero
  * clears the setting.  Host-only; PH_EINVAL on bad values.  A kernel that
@@ -233,13 +234,32 @@ int ph_track(const ph_system *target, const ph_system *start, const double gamma
  *   path_ids : host int64[path_off[nsys]] multi-index numbers of the tracked
  *              start solutions of each system, or NULL (0 .. npaths_s - 1)
  *   x_end, status, reason, steps : indexed by the global path index (ld >= total)
- * Lanes per path are the next power of two >= the largest n of the batch.
+ * A path takes the next power of two >= its system's n lanes (4, 8, 16 or
+ * 32); systems of one lane count share a work queue and a range of
+ * workgroups sized by their share of the work.
  * Same synchrony, scratch and errors as ph_track.
  */
 int ph_track_batch(int32_t nsys, const ph_system *const *targets, const double *gammas,
                    const int64_t *path_off, const int64_t *path_ids, const ph_track_opts *opts,
                    double *x_end, int64_t ld, int8_t *status, int8_t *reason, int32_t *steps,
                    ph_track_report *rep, void *stream);
+
+/*
+ * ph_track_autotune -- choose the launch shape of ph_track_batch (and of
+ * ph_track with a total-degree start) for this batch: tracks a sample of
+ * about `sample` paths (each system's first ones, in proportion to its path
+ * count) under each candidate (schedule, rounds_per_launch, blocks_per_cu)
+ * and writes *opts with the fastest into *tuned (every other field copied).
+ * With PH_AUTOTUNE_CACHE naming a file, a previous choice for the same
+ * systems, path counts, prec and mixed is read from it instead of timing, and
+ * a new choice is appended.  best_seconds (nullable) receives the sample's
+ * time under the choice (0 when read from the file).  Allocates and frees
+ * its own device outputs; synchronous.  Errors as ph_track_batch.
+ */
+int ph_track_autotune(int32_t nsys, const ph_system *const *targets, const double *gammas,
+                      const int64_t *path_off, const int64_t *path_ids,
+                      const ph_track_opts *opts, int64_t sample, ph_track_opts *tuned,
+                      double *best_seconds, void *stream);
 
 /* Message of the last failure on the calling thread ("" if none). */
 const char *ph_last_error(void);

@@ -25,10 +25,10 @@ REASONS = {0: "NONE", 1: "SUCCESS", 2: "DIVERGED", 3: "STEP_UNDERFLOW", 4: "MAX_
 EXPORTED = ["ph_system_create", "ph_system_destroy", "ph_system_info", "ph_system_degrees",
             "ph_start_solutions", "ph_eval_jac", "ph_track_opts_default", "ph_last_error",
             "ph_arith_probe", "ph_track", "ph_track_batch", "ph_eval_set_config",
-            "ph_eval_autotune"]
+            "ph_eval_autotune", "ph_track_autotune"]
 
 # ph_eval_set_config kernels
-EVAL_AUTO, EVAL_GENERAL, EVAL_REGROW, EVAL_FAST = 0, 1, 2, 3
+EVAL_AUTO, EVAL_GENERAL, EVAL_REGROW, EVAL_FAST, EVAL_FAST_VECROW = 0, 1, 2, 3, 4
 
 
 class TrackOpts(ctypes.Structure):
@@ -99,6 +99,7 @@ def load_library(path: str = LIB_PATH):
     L.ph_track_batch.argtypes = [i32, P, P, P, P, P, P, i64, P, P, P, P, P]
     L.ph_eval_set_config.argtypes = [P, P, i32, i32, i32, i32]
     L.ph_eval_autotune.argtypes = [P, P, P, i32, i64, P, P, i64, P, P, P, P]
+    L.ph_track_autotune.argtypes = [i32, P, P, P, P, P, i64, P, P, P]
     for name in EXPORTED:
         fn = getattr(L, name)
         if name != "ph_last_error":
@@ -301,13 +302,7 @@ def track(sys: System, gamma, npaths: int, opts: TrackOpts | None = None, x_star
                 report=rep.as_dict())
 
 
-def track_batch(systems, gammas, path_lists, opts: TrackOpts | None = None, stream=None):
-    """Track the given start-solution indices of several systems in one launch
-    (ph_track_batch).  path_lists[s]: int array of multi-index numbers or None
-    for every start solution of system s.  Global path order = concatenation."""
-    torch = _torch()
-    opts = opts or track_opts()
-    L = opts.prec
+def _batch_arrays(systems, gammas, path_lists):
     nsys = len(systems)
     counts, ids = [], []
     any_ids = any(p is not None for p in path_lists)
@@ -323,13 +318,24 @@ def track_batch(systems, gammas, path_lists, opts: TrackOpts | None = None, stre
             ids.append(p)
     off = np.zeros(nsys + 1, dtype=np.int64)
     off[1:] = np.cumsum(counts)
-    total = int(off[-1])
     pid = np.ascontiguousarray(np.concatenate(ids)) if any_ids else None
-    nmax = max(s.n_var for s in systems)
-    x_end, status, reason, steps = _track_outputs(torch, nmax * 2 * L, total, total)
     handles = (ctypes.c_void_p * nsys)(*[s.handle.value for s in systems])
     gam = np.ascontiguousarray([[complex(g).real, complex(g).imag] for g in gammas],
                                dtype=np.float64)
+    return nsys, handles, gam, off, pid
+
+
+def track_batch(systems, gammas, path_lists, opts: TrackOpts | None = None, stream=None):
+    """Track the given start-solution indices of several systems in one launch
+    (ph_track_batch).  path_lists[s]: int array of multi-index numbers or None
+    for every start solution of system s.  Global path order = concatenation."""
+    torch = _torch()
+    opts = opts or track_opts()
+    L = opts.prec
+    nsys, handles, gam, off, pid = _batch_arrays(systems, gammas, path_lists)
+    total = int(off[-1])
+    nmax = max(s.n_var for s in systems)
+    x_end, status, reason, steps = _track_outputs(torch, nmax * 2 * L, total, total)
     rep = TrackReport()
     _check(load_library().ph_track_batch(nsys, handles, gam.ctypes.data, off.ctypes.data,
                                          None if pid is None else pid.ctypes.data,
@@ -339,3 +345,20 @@ def track_batch(systems, gammas, path_lists, opts: TrackOpts | None = None, stre
     return dict(x_end=x_end, status=status[:total].cpu().numpy(),
                 reason=reason[:total].cpu().numpy(), steps=steps[:total].cpu().numpy(),
                 report=rep.as_dict(), path_off=off)
+
+
+def track_autotune(systems, gammas, path_lists, opts: TrackOpts | None = None,
+                   sample: int = 16384, stream=None):
+    """Launch shape (schedule, rounds_per_launch, blocks_per_cu) for this batch,
+    timed on a proportional sample of its paths (ph_track_autotune).
+    Returns (tuned TrackOpts, seconds of the sample under it; 0 from the cache)."""
+    _torch()
+    opts = opts or track_opts()
+    nsys, handles, gam, off, pid = _batch_arrays(systems, gammas, path_lists)
+    tuned = TrackOpts()
+    sec = ctypes.c_double(0.0)
+    _check(load_library().ph_track_autotune(nsys, handles, gam.ctypes.data, off.ctypes.data,
+                                            None if pid is None else pid.ctypes.data,
+                                            ctypes.byref(opts), sample, ctypes.byref(tuned),
+                                            ctypes.byref(sec), _stream(stream)))
+    return tuned, sec.value

@@ -308,6 +308,66 @@ __device__ __forceinline__ void regrow_fma(RegRow &r, int j, double e, const C<1
     r.ih[j] = (unsigned)(yb >> 32);
 }
 
+// The same row held by the compiler (four indexed planes, see RegRow).
+struct VecRow {
+    RegRow r;
+    __device__ __forceinline__ void zero()
+    {
+        r.rl = 0;
+        r.rh = 0;
+        r.il = 0;
+        r.ih = 0;
+    }
+    __device__ __forceinline__ void fma(int j2, double e, const C<1> &d) { regrow_fma(r, j2 >> 1, e, d); }
+    __device__ __forceinline__ void get(int j, double &re, double &im)
+    {
+        re = __builtin_bit_cast(double, ((unsigned long long)r.rh[j] << 32) | r.rl[j]);
+        im = __builtin_bit_cast(double, ((unsigned long long)r.ih[j] << 32) | r.il[j]);
+    }
+};
+
+// The row pinned in the upper half of the register file: real parts of
+// columns 0..31 in v[128:191], imaginary parts in v[192:255].  The kernel is
+// compiled with a 128-register budget, so the compiler never allocates these
+// registers; every statement that touches them lists all of them as
+// clobbered (which also makes the kernel descriptor reserve 256 registers).
+// A partial is added with the column index applied by the GPR indexing mode
+// to the destination and addend of two FP64 FMAs: no register moves at all.
+// fma takes twice the column index; callers guarantee 0 <= j < 32 (the fast
+// path requires n_var <= 32).
+#define PH_PIN_CLOBBERS "v128","v129","v130","v131","v132","v133","v134","v135","v136","v137","v138","v139","v140","v141","v142","v143","v144","v145","v146","v147","v148","v149","v150","v151","v152","v153","v154","v155","v156","v157","v158","v159","v160","v161","v162","v163","v164","v165","v166","v167","v168","v169","v170","v171","v172","v173","v174","v175","v176","v177","v178","v179","v180","v181","v182","v183","v184","v185","v186","v187","v188","v189","v190","v191","v192","v193","v194","v195","v196","v197","v198","v199","v200","v201","v202","v203","v204","v205","v206","v207","v208","v209","v210","v211","v212","v213","v214","v215","v216","v217","v218","v219","v220","v221","v222","v223","v224","v225","v226","v227","v228","v229","v230","v231","v232","v233","v234","v235","v236","v237","v238","v239","v240","v241","v242","v243","v244","v245","v246","v247","v248","v249","v250","v251","v252","v253","v254","v255"
+struct PinRow {
+    __device__ __forceinline__ void zero()
+    {
+        asm volatile("v_mov_b64 v[128:129], 0\n\tv_mov_b64 v[130:131], 0\n\tv_mov_b64 v[132:133], 0\n\tv_mov_b64 v[134:135], 0\n\tv_mov_b64 v[136:137], 0\n\tv_mov_b64 v[138:139], 0\n\tv_mov_b64 v[140:141], 0\n\tv_mov_b64 v[142:143], 0\n\tv_mov_b64 v[144:145], 0\n\tv_mov_b64 v[146:147], 0\n\tv_mov_b64 v[148:149], 0\n\tv_mov_b64 v[150:151], 0\n\tv_mov_b64 v[152:153], 0\n\tv_mov_b64 v[154:155], 0\n\tv_mov_b64 v[156:157], 0\n\tv_mov_b64 v[158:159], 0\n\tv_mov_b64 v[160:161], 0\n\tv_mov_b64 v[162:163], 0\n\tv_mov_b64 v[164:165], 0\n\tv_mov_b64 v[166:167], 0\n\tv_mov_b64 v[168:169], 0\n\tv_mov_b64 v[170:171], 0\n\tv_mov_b64 v[172:173], 0\n\tv_mov_b64 v[174:175], 0\n\tv_mov_b64 v[176:177], 0\n\tv_mov_b64 v[178:179], 0\n\tv_mov_b64 v[180:181], 0\n\tv_mov_b64 v[182:183], 0\n\tv_mov_b64 v[184:185], 0\n\tv_mov_b64 v[186:187], 0\n\tv_mov_b64 v[188:189], 0\n\tv_mov_b64 v[190:191], 0\n\tv_mov_b64 v[192:193], 0\n\tv_mov_b64 v[194:195], 0\n\tv_mov_b64 v[196:197], 0\n\tv_mov_b64 v[198:199], 0\n\tv_mov_b64 v[200:201], 0\n\tv_mov_b64 v[202:203], 0\n\tv_mov_b64 v[204:205], 0\n\tv_mov_b64 v[206:207], 0\n\tv_mov_b64 v[208:209], 0\n\tv_mov_b64 v[210:211], 0\n\tv_mov_b64 v[212:213], 0\n\tv_mov_b64 v[214:215], 0\n\tv_mov_b64 v[216:217], 0\n\tv_mov_b64 v[218:219], 0\n\tv_mov_b64 v[220:221], 0\n\tv_mov_b64 v[222:223], 0\n\tv_mov_b64 v[224:225], 0\n\tv_mov_b64 v[226:227], 0\n\tv_mov_b64 v[228:229], 0\n\tv_mov_b64 v[230:231], 0\n\tv_mov_b64 v[232:233], 0\n\tv_mov_b64 v[234:235], 0\n\tv_mov_b64 v[236:237], 0\n\tv_mov_b64 v[238:239], 0\n\tv_mov_b64 v[240:241], 0\n\tv_mov_b64 v[242:243], 0\n\tv_mov_b64 v[244:245], 0\n\tv_mov_b64 v[246:247], 0\n\tv_mov_b64 v[248:249], 0\n\tv_mov_b64 v[250:251], 0\n\tv_mov_b64 v[252:253], 0\n\tv_mov_b64 v[254:255], 0" ::: PH_PIN_CLOBBERS);
+    }
+    __device__ __forceinline__ void fma(int j2, double e, const C<1> &d)
+    {
+        asm volatile("s_set_gpr_idx_on %0, gpr_idx(SRC2,DST)\n\t"
+                     "v_fma_f64 v[128:129], %1, %2, v[128:129]\n\t"
+                     "v_fma_f64 v[192:193], %1, %3, v[192:193]\n\t"
+                     "s_set_gpr_idx_off"
+                     :
+                     : "s"(j2), "s"(e), "v"(d.re.v[0]), "v"(d.im.v[0])
+                     : PH_PIN_CLOBBERS);
+    }
+    __device__ __forceinline__ void get(int j, double &re, double &im)
+    {
+        unsigned rl, rh, il, ih;
+        asm volatile("s_set_gpr_idx_on %4, gpr_idx(SRC0)\n\t"
+                     "v_mov_b32 %0, v128\n\t"
+                     "v_mov_b32 %1, v129\n\t"
+                     "v_mov_b32 %2, v192\n\t"
+                     "v_mov_b32 %3, v193\n\t"
+                     "s_set_gpr_idx_off"
+                     : "=v"(rl), "=v"(rh), "=v"(il), "=v"(ih)
+                     : "s"(2 * j)
+                     : PH_PIN_CLOBBERS);
+        re = __builtin_bit_cast(double, ((unsigned long long)rh << 32) | rl);
+        im = __builtin_bit_cast(double, ((unsigned long long)ih << 32) | il);
+    }
+};
+
 // Scalar copy of the part of a record the sweep needs first.
 struct DHead {
     double cre, cim;
@@ -330,18 +390,18 @@ __device__ __forceinline__ DHead dfast_head(const DTerm *__restrict__ r)
 // One term with exactly K factors.  The head of the NEXT record (same K run)
 // is fetched once the coordinates of this term are in registers, so its
 // scalar-load latency overlaps the backward products.
-template <int K>
+template <int K, class Row>
 __device__ __forceinline__ void dfast_sweep(const DHead &h, const DTerm *__restrict__ r,
                                             const DTerm *__restrict__ rnext, DHead &hnext,
                                             const char *__restrict__ xb, int lane, C<1> cf,
-                                            RegRow &row, C<1> &v)
+                                            Row &row, C<1> &v)
 {
     C<1> xv[K];
     C<1> q[K];
 #pragma unroll
     for (int l = 0; l < K; ++l) {
         const uint32_t wl = h.w[l];
-        xv[l] = ldsc(xb, (wl & 0xffffu) * 1024u, lane);
+        xv[l] = ldsc(xb, (wl & 0xffffu) * 512u, lane);
         cf = c_mul<1>(cf, ldsc(xb, (wl >> 16) * 8u, lane));
     }
     q[0] = cf;
@@ -353,17 +413,18 @@ __device__ __forceinline__ void dfast_sweep(const DHead &h, const DTerm *__restr
 #pragma unroll
     for (int l = 0; l < K; ++l) ae[l] = r->a[l];
     C<1> sfx = xv[K - 1];
-    regrow_fma(row, (int)(h.w[K - 1] & 0xffffu), ae[K - 1], q[K - 1]);
+    row.fma((int)(h.w[K - 1] & 0xffffu), ae[K - 1], q[K - 1]);
 #pragma unroll
     for (int l = K - 2; l >= 0; --l) {
-        regrow_fma(row, (int)(h.w[l] & 0xffffu), ae[l], c_mul<1>(q[l], sfx));
+        row.fma((int)(h.w[l] & 0xffffu), ae[l], c_mul<1>(q[l], sfx));
         if (l > 0) sfx = c_mul<1>(sfx, xv[l]);
     }
 }
 
-__global__ void __launch_bounds__(512) eval_d_fast_kernel(EvalArgs a, const int32_t *__restrict__ d_run,
-                                                          const DTerm *__restrict__ dterm,
-                                                          const int32_t *__restrict__ d_deg, int planes)
+template <class Row>
+__device__ __forceinline__ void dfast_body(const EvalArgs &a, const int32_t *__restrict__ d_run,
+                                           const DTerm *__restrict__ dterm,
+                                           const int32_t *__restrict__ d_deg, int planes)
 {
     extern __shared__ double xl[];
     const char *xb = reinterpret_cast<const char *>(xl);
@@ -396,11 +457,8 @@ __global__ void __launch_bounds__(512) eval_d_fast_kernel(EvalArgs a, const int3
     if (a.t) gs = c_mul_d<1>(c_from<1>(a.gre, a.gim), 1.0 - tv);
 
     for (int i = blockIdx.y * W + w; i < a.n_eq; i += a.eq_stride) {
-        RegRow row;
-        row.rl = 0;
-        row.rh = 0;
-        row.il = 0;
-        row.ih = 0;
+        Row row;
+        row.zero();
         C<1> v = c_zero<1>();
         const int32_t *run = d_run + i * 10;
         auto coef = [&](const DTerm *r) -> C<1> {
@@ -440,7 +498,7 @@ __global__ void __launch_bounds__(512) eval_d_fast_kernel(EvalArgs a, const int3
                 if (e > 1) base = c_mul<1>(base, base);
             }
             v = c_add<1>(v, c_mul<1>(gs, c_sub<1>(c_mul<1>(pw, xi), c_from<1>(1.0, 0.0))));
-            regrow_fma(row, i, (double)d, c_mul<1>(gs, pw));
+            row.fma(2 * i, (double)d, c_mul<1>(gs, pw));
         }
         if (act) {
             a.val[((int64_t)(i * 2 + 0)) * a.ld + p] = v.re.v[0];
@@ -449,14 +507,30 @@ __global__ void __launch_bounds__(512) eval_d_fast_kernel(EvalArgs a, const int3
 #pragma unroll
             for (int j = 0; j < 32; ++j) {
                 if (j < nv) {
-                    jr[(int64_t)(j * 2 + 0) * a.ld] =
-                        __builtin_bit_cast(double, ((unsigned long long)row.rh[j] << 32) | row.rl[j]);
-                    jr[(int64_t)(j * 2 + 1) * a.ld] =
-                        __builtin_bit_cast(double, ((unsigned long long)row.ih[j] << 32) | row.il[j]);
+                    double re, im;
+                    row.get(j, re, im);
+                    jr[(int64_t)(j * 2 + 0) * a.ld] = re;
+                    jr[(int64_t)(j * 2 + 1) * a.ld] = im;
                 }
             }
         }
     }
+}
+
+__global__ void __launch_bounds__(512) eval_d_fast_kernel(EvalArgs a, const int32_t *__restrict__ d_run,
+                                                          const DTerm *__restrict__ dterm,
+                                                          const int32_t *__restrict__ d_deg, int planes)
+{
+    dfast_body<VecRow>(a, d_run, dterm, d_deg, planes);
+}
+
+// The same with the row pinned in v[128:255] (PinRow); everything else of
+// the kernel lives in the lower 128 registers.
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_num_vgpr(128)))
+eval_d_pinned_kernel(EvalArgs a, const int32_t *__restrict__ d_run, const DTerm *__restrict__ dterm,
+                     const int32_t *__restrict__ d_deg, int planes)
+{
+    dfast_body<PinRow>(a, d_run, dterm, d_deg, planes);
 }
 
 template <int L, int KMAX, bool XLDS, bool JAC>
@@ -516,7 +590,8 @@ int eval_launch(const DevTable &tab, const double gamma[2], int prec, int64_t np
     const bool can_fast = prec == 1 && wj && tab.n_var <= 32 && tab.dfast;
     const bool can_reg = prec == 1 && wj && tab.n_var <= 32 && tab.kmax <= 16;
     int kernel = cfg ? cfg->kernel : 0;
-    if (kernel == 3 && !can_fast) return fail(PH_EUNSUPPORTED, "fast path not available for this system");
+    if ((kernel == 3 || kernel == 4) && !can_fast)
+        return fail(PH_EUNSUPPORTED, "fast path not available for this system");
     if (kernel == 2 && !can_reg) return fail(PH_EUNSUPPORTED, "register-row kernel not available");
     if (kernel == 0) kernel = can_fast ? 3 : (can_reg ? 2 : 1);
     // waves per workgroup: all of them share the 64 points staged in LDS and
@@ -535,12 +610,16 @@ int eval_launch(const DevTable &tab, const double gamma[2], int prec, int64_t np
     a.eq_stride = G * W;
     dim3 grid((unsigned)blocks, (unsigned)G);
     const size_t lds = (size_t)tab.n_var * 2 * prec * 64 * sizeof(double);
-    if (kernel == 3) {
+    if (kernel == 3 || kernel == 4) {
         const size_t ldsf = ((size_t)tab.dfast_planes * tab.n_var * 2 + 2) * 64 * sizeof(double);
-        hipLaunchKernelGGL(eval_d_fast_kernel, grid, dim3(64 * W), ldsf, st, a, tab.d_run, tab.dterm,
-                           tab.d_deg, tab.dfast_planes);
+        if (kernel == 3)
+            hipLaunchKernelGGL(eval_d_pinned_kernel, grid, dim3(64 * W), ldsf, st, a, tab.d_run,
+                               tab.dterm, tab.d_deg, tab.dfast_planes);
+        else
+            hipLaunchKernelGGL(eval_d_fast_kernel, grid, dim3(64 * W), ldsf, st, a, tab.d_run,
+                               tab.dterm, tab.d_deg, tab.dfast_planes);
         hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return hip_fail(e, "eval_d_fast_kernel launch");
+        if (e != hipSuccess) return hip_fail(e, "fast-path kernel launch");
         return PH_OK;
     }
     if (kernel == 2) {
@@ -638,8 +717,8 @@ extern "C" int ph_eval_set_config(ph_system *target, const ph_system *start, int
 {
     if (!target) return fail(PH_EINVAL, "null target system");
     if (prec != 1 && prec != 2 && prec != 4) return fail(PH_EINVAL, "prec must be 1, 2 or 4");
-    if (kernel < 0 || kernel > 3 || waves < 0 || waves > 8 || groups < 0)
-        return fail(PH_EINVAL, "kernel must be 0..3, waves 0..8, groups >= 0");
+    if (kernel < 0 || kernel > 4 || waves < 0 || waves > 8 || groups < 0)
+        return fail(PH_EINVAL, "kernel must be 0..4, waves 0..8, groups >= 0");
     std::lock_guard<std::mutex> lk(target->mu);
     if (kernel == 0 && waves == 0 && groups == 0)
         target->eval_cfg.erase({start, prec});
@@ -665,7 +744,7 @@ extern "C" int ph_eval_autotune(ph_system *target, const ph_system *start, const
     PH_HIP(hipEventCreate(&e1));
     EvalCfg best;
     double best_t = 1e300;
-    const int kernels[3] = {3, 2, 1};
+    const int kernels[4] = {3, 4, 2, 1};
     for (int kk : kernels) {
         for (int W = 1; W <= 8; W *= 2) {
             for (int G = 1; G <= 8; G *= 2) {

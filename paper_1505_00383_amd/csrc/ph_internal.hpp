@@ -44,7 +44,7 @@ int hip_fail(hipError_t e, const char *what);
 struct DTerm {
     double cre, cim;
     int32_t k, sel;
-    uint32_t w[8];
+    uint32_t w[8];  // 2 * variable | (LDS offset of x^(a-1), or of the ones row, / 8) << 16
     int32_t pad[2];
     double a[8];
 };
@@ -71,7 +71,8 @@ struct DevTable {
 
 // Kernel choice and tiling of one evaluation: kernel 0 automatic, 1 general
 // (Jacobian row accumulated in the output), 2 register row (double, n <= 32),
-// 3 double fast path; W waves per workgroup, G equation groups (0: default).
+// 3 double fast path with the row pinned in the upper registers, 4 the same
+// with a compiler-held row; W waves per workgroup, G equation groups (0: default).
 struct EvalCfg {
     int kernel = 0, W = 0, G = 0;
 };

@@ -141,7 +141,7 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
                 for (int q = a; q < b; ++q) {
                     int l = q - a, v = sy.fac_var[q], e = sy.fac_exp[q];
                     const uint32_t poff = e == 1 ? ones_off : uint32_t(((e - 2) * nv + v) * 2 * 64 * 8);
-                    r.w[l] = uint32_t(v) | ((poff / 8) << 16);
+                    r.w[l] = uint32_t(2 * v) | ((poff / 8) << 16);
                     r.a[l] = double(e);
                 }
                 dterm.push_back(r);

@@ -71,8 +71,10 @@ int clear_counter_launch(unsigned int *c, hipStream_t st)
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+#include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <vector>
@@ -379,4 +381,114 @@ extern "C" int ph_track_batch(int32_t nsys, const ph_system *const *targets, con
 {
     return track_impl(nsys, targets, nullptr, gammas, path_off, path_ids, nullptr, ld, opts, x_end,
                       status, reason, steps, rep, (hipStream_t)stream);
+}
+
+// Autotuning of the tracker's launch shape on a proportional sample.
+extern "C" int ph_track_autotune(int32_t nsys, const ph_system *const *targets, const double *gammas,
+                                 const int64_t *path_off, const int64_t *path_ids,
+                                 const ph_track_opts *opts, int64_t sample, ph_track_opts *tuned,
+                                 double *best_seconds, void *stream)
+{
+    if (!opts || !tuned) return fail(PH_EINVAL, "null opts or tuned");
+    int rc = check_opts(*opts);
+    if (rc) return rc;
+    if (nsys < 1 || !targets || !gammas || !path_off) return fail(PH_EINVAL, "null batch arrays");
+    if (path_off[0] != 0) return fail(PH_EINVAL, "path_off[0] must be 0");
+    for (int s = 0; s < nsys; ++s) {
+        if (!targets[s]) return fail(PH_EINVAL, "null target system");
+        if (path_off[s + 1] < path_off[s]) return fail(PH_EINVAL, "path_off not monotone");
+    }
+    const int64_t total = path_off[nsys];
+    if (total == 0 || sample < 1) return fail(PH_EINVAL, "autotuning needs paths and sample >= 1");
+    hipStream_t st = (hipStream_t)stream;
+    if (best_seconds) *best_seconds = 0;
+
+    // key: systems, their path counts, precision and mixed
+    uint64_t key = 1469598103934665603ull;
+    auto mix = [&key](uint64_t v) {
+        for (int b = 0; b < 8; ++b) key = (key ^ ((v >> (8 * b)) & 0xff)) * 1099511628211ull;
+    };
+    for (int s = 0; s < nsys; ++s) {
+        mix(targets[s]->h.fingerprint);
+        mix((uint64_t)(path_off[s + 1] - path_off[s]));
+    }
+    mix((uint64_t)opts->prec);
+    mix((uint64_t)opts->mixed);
+    const char *cache = std::getenv("PH_AUTOTUNE_CACHE");
+    if (cache) {
+        if (FILE *f = std::fopen(cache, "r")) {
+            char tag[16];
+            unsigned long long k = 0;
+            int sch = 0, rnd = 0, bpc = 0;
+            double sec = 0;
+            bool found = false;
+            ph_track_opts o = *opts;
+            while (std::fscanf(f, "%15s %llx %d %d %d %lf", tag, &k, &sch, &rnd, &bpc, &sec) == 6) {
+                if (std::strcmp(tag, "track") == 0 && k == key) {
+                    o.schedule = sch;
+                    o.rounds_per_launch = rnd;
+                    o.blocks_per_cu = bpc;
+                    found = true;
+                }
+            }
+            std::fclose(f);
+            if (found) {
+                *tuned = o;
+                return PH_OK;
+            }
+        }
+    }
+
+    // proportional sample: each system's first paths (or first listed ids)
+    const double frac = std::min(1.0, (double)sample / (double)total);
+    std::vector<int64_t> off(nsys + 1, 0), ids;
+    for (int s = 0; s < nsys; ++s) {
+        const int64_t np = path_off[s + 1] - path_off[s];
+        const int64_t m = np == 0 ? 0 : std::max<int64_t>(1, (int64_t)std::ceil(np * frac));
+        for (int64_t p = 0; p < m; ++p) ids.push_back(path_ids ? path_ids[path_off[s] + p] : p);
+        off[s + 1] = off[s] + m;
+    }
+    const int64_t ns = off[nsys];
+    int maxn = 1;
+    for (int s = 0; s < nsys; ++s) maxn = std::max(maxn, (int)targets[s]->h.n_var);
+    DevBuf bx, bst;
+    PH_HIP(hipMalloc(&bx.p, sizeof(double) * (size_t)maxn * 2 * opts->prec * ns));
+    PH_HIP(hipMalloc(&bst.p, (size_t)ns));
+
+    // candidates: residency-limited workgroups per CU, both schedules
+    int np_max = 4;
+    while (np_max < maxn) np_max *= 2;
+    const size_t lds = track_lds_bytes(opts->prec, opts->mixed, np_max);
+    const int lds_cap = (int)std::max<size_t>(1, (160 * 1024) / lds);
+    struct Cand { int sch, rnd, bpc; };
+    std::vector<Cand> cands;
+    for (int bpc : {2, 4, 8, 12, 16})
+        if (bpc <= lds_cap || bpc == 2) cands.push_back({PH_SCHED_PERSISTENT, opts->rounds_per_launch, bpc});
+    for (int rnd : {4, 16}) cands.push_back({PH_SCHED_GRAPH, rnd, std::min(8, lds_cap)});
+    double best = 1e300;
+    ph_track_opts bo = *opts;
+    for (const Cand &c : cands) {
+        ph_track_opts o = *opts;
+        o.schedule = c.sch;
+        o.rounds_per_launch = c.rnd;
+        o.blocks_per_cu = c.bpc;
+        ph_track_report r;
+        rc = track_impl(nsys, targets, nullptr, gammas, off.data(), ids.data(), nullptr, ns, &o,
+                        (double *)bx.p, (int8_t *)bst.p, nullptr, nullptr, &r, st);
+        if (rc) return rc;
+        if (r.seconds < best) {
+            best = r.seconds;
+            bo = o;
+        }
+    }
+    *tuned = bo;
+    if (best_seconds) *best_seconds = best;
+    if (cache) {
+        if (FILE *f = std::fopen(cache, "a")) {
+            std::fprintf(f, "track %llx %d %d %d %.6f\n", (unsigned long long)key, bo.schedule,
+                         bo.rounds_per_launch, bo.blocks_per_cu, best);
+            std::fclose(f);
+        }
+    }
+    return PH_OK;
 }

@@ -76,6 +76,7 @@ def test_validation_errors_before_any_device_call(lib):
     assert rc == -1 and b"coef_limbs" in lib.ph_last_error()
     assert lib.ph_eval_jac(None, None, None, 1, 1, None, None, 1, None, None, None) == -1
     assert lib.ph_eval_set_config(None, None, 1, 0, 0, 0) == -1
+    assert lib.ph_track_autotune(1, None, None, None, None, None, 1, None, None, None) == -1
     assert lib.ph_eval_autotune(None, None, None, 1, 1, None, None, 1, None, None, None,
                                 None) == -1
 

@@ -1,6 +1,6 @@
 """GPU parity of ph_track / ph_track_batch against the oracle's tracker.
 
-Endpoint parity (SURVEY C-6): ||x_gpu - x_ref||_inf / max(1, ||x_ref||_inf) <= 1e-8
+Endpoint parity: ||x_gpu - x_ref||_inf / max(1, ||x_ref||_inf) <= 1e-8
 after polishing, where x_ref is the oracle's PLAIN track at the same precision.
 When the two disagree on a path, the oracle re-tracks it with h_max / 10; the GPU
 endpoint must then agree with the re-track (the other one jumped paths).
@@ -236,3 +236,67 @@ def test_batch_lane_classes(schedule):
         rel = _rel(X[sl, :sy.n_var][ok], ref["x"][ok])
         print(f"[gpu] class batch n={sy.n_var} paths={len(paths[k])} max_rel={rel.max():.1e}", flush=True)
         assert np.all(rel <= 1e-8)
+
+
+def _distinct(X, ok):
+    Z = X[ok][..., 0, 0] + 1j * X[ok][..., 1, 0]
+    key = np.round(Z / 1e-6)
+    return len(np.unique(np.concatenate([key.real, key.imag], axis=1), axis=0)) == len(Z)
+
+
+def test_quadratic16_full_65536_paths_qd_mixed():
+    """The full n = 16, degree-2 workload (2^16 paths, QD residual, FP64
+    Newton solves) in the launch the benchmark times: sampled endpoints
+    against the oracle's plain QD track, all successful endpoints pairwise
+    distinct, and the failures counted by reason."""
+    s = synth.tracking_quadratic16()
+    g = synth.gamma_of(s)
+    S = ph.System(s)
+    B = 2 ** 16
+    res = ph.track(S, g, B, ph.track_opts(prec=4, mixed=1))
+    rep = res["report"]
+    print(f"[gpu] n16 d2 full: {rep}", flush=True)
+    ok = res["status"] == 1
+    assert ok.sum() >= 0.99 * B
+    assert rep["n_success"] == ok.sum() and rep["n_fail"] == B - ok.sum()
+    X = _x_end(res, 16, 4, B)
+    assert _distinct(X, ok)
+    sample = np.array([0, 1, 12345, 32768, 54321, B - 1])
+    sub = {"status": res["status"][sample], "steps": res["steps"][sample]}
+    ref = oracle.track(s, g, sample, oracle.Opts(prec=4), threads=THREADS)
+    both = (sub["status"] == 1) & (ref["status"] == 1)
+    assert both.sum() >= len(sample) - 1
+    assert np.all(_rel(X[sample][both], ref["x"][both]) <= 1e-8)
+
+
+def test_batch_full_workload_graph_schedule():
+    """64 systems with n in 4..16, about 200k paths, DD residual with FP64
+    solves, one launch under the graph schedule: sampled paths of eight
+    systems against the oracle, every fully tracked system's endpoints
+    pairwise distinct, and the report consistent with the status array."""
+    sysms, gammas, paths, cap = synth.batch_heterogeneous()
+    systems = [ph.System(s) for s in sysms]
+    opts = ph.track_opts(prec=2, mixed=1, schedule=ph.SCHED_GRAPH)
+    res = ph.track_batch(systems, gammas, paths, opts)
+    off = res["path_off"]
+    total = int(off[-1])
+    rep = res["report"]
+    print(f"[gpu] batch64: paths={total} cap={cap} {rep}", flush=True)
+    assert total >= 200_000
+    ok = res["status"] == 1
+    assert rep["n_success"] == ok.sum() and ok.mean() >= 0.99
+    X = _x_end(res, 16, 2, total)
+    for k, s in enumerate(sysms):
+        sl = slice(off[k], off[k + 1])
+        bez = int(np.prod(s.degrees().astype(np.int64)))
+        if len(paths[k]) == bez and ok[sl].all():
+            assert _distinct(X[sl, :s.n_var], ok[sl]), k
+    rng = np.random.default_rng(17)
+    for k in rng.choice(len(sysms), size=8, replace=False):
+        s = sysms[k]
+        j = int(rng.integers(0, len(paths[k])))
+        ref = oracle.track(s, gammas[k], paths[k][j:j + 1], oracle.Opts(prec=2), threads=1)
+        gi = int(off[k]) + j
+        if ref["status"][0] == 1 and res["status"][gi] == 1:
+            r = _rel(X[gi:gi + 1, :s.n_var], ref["x"])[0]
+            assert r <= 1e-8, (int(k), j, r)

@@ -43,7 +43,8 @@ def test_every_configuration_matches_oracle(L):
     g = synth.gamma_of(s)
     ov, oj, sv, sj = oracle.eval_homotopy(s, L, x, t, g)
     S = ph.System(s)
-    kernels = [ph.EVAL_GENERAL] + ([ph.EVAL_REGROW, ph.EVAL_FAST] if L == 1 else [])
+    kernels = [ph.EVAL_GENERAL] + ([ph.EVAL_REGROW, ph.EVAL_FAST, ph.EVAL_FAST_VECROW]
+                                  if L == 1 else [])
     worst = 0.0
     for k in kernels:
         for W in (1, 2, 4, 8):
@@ -89,7 +90,7 @@ def test_autotune_choice_persists_in_cache_file(tmp_path, monkeypatch):
     assert ms > 0
     lines = cache.read_text().split("\n")
     fields = lines[0].split()
-    assert fields[0] == "eval" and int(fields[3]) == L and int(fields[4]) in (1, 2, 3)
+    assert fields[0] == "eval" and int(fields[3]) == L and int(fields[4]) in (1, 2, 3, 4)
     print(f"[gpu] autotune -> {lines[0]}", flush=True)
     # the tuned configuration still gives oracle-exact results
     idx = np.array([0, 1, 63, 64, 2000, npts - 1])
@@ -116,3 +117,32 @@ def test_autotune_choice_persists_in_cache_file(tmp_path, monkeypatch):
     cache.write_text(" ".join(last) + "\n")
     with pytest.raises(ph.PHError, match="-4"):
         _eval(ph.System(s3), s3, 2, x3, t3, g)
+
+
+def test_track_autotune_choice_is_valid_and_cached(tmp_path, monkeypatch):
+    """The tuned launch shape changes only the schedule: endpoints, status and
+    step counts are bitwise those of the default shape; a second call reads
+    the choice back from the cache file."""
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("PH_AUTOTUNE_CACHE", str(cache))
+    small, cub = synth.tracking_small(), synth.tracking_cubic()
+    systems = [ph.System(small), ph.System(cub)]
+    gammas = [synth.gamma_of(small), synth.gamma_of(cub)]
+    paths = [None, np.arange(0, 6561, 7)]
+    base = ph.track_opts(prec=2, mixed=1)
+    tuned, sec = ph.track_autotune(systems, gammas, paths, base, sample=400)
+    assert sec > 0
+    assert tuned.schedule in (ph.SCHED_PERSISTENT, ph.SCHED_GRAPH)
+    assert 1 <= tuned.blocks_per_cu <= 16 and tuned.rounds_per_launch >= 1
+    assert (tuned.prec, tuned.mixed, tuned.h_max) == (2, 1, base.h_max)
+    print(f"[gpu] tuned schedule={tuned.schedule} rounds={tuned.rounds_per_launch} "
+          f"blocks_per_cu={tuned.blocks_per_cu} sample {sec:.3f} s", flush=True)
+    a = ph.track_batch(systems, gammas, paths, base)
+    b = ph.track_batch(systems, gammas, paths, tuned)
+    assert (a["status"] == b["status"]).all() and (a["steps"] == b["steps"]).all()
+    import torch
+    assert torch.equal(a["x_end"], b["x_end"])
+    again, sec2 = ph.track_autotune(systems, gammas, paths, base, sample=400)
+    assert sec2 == 0.0
+    assert (again.schedule, again.rounds_per_launch, again.blocks_per_cu) == \
+        (tuned.schedule, tuned.rounds_per_launch, tuned.blocks_per_cu)
