@@ -38,6 +38,32 @@ CSCALE = {1: 2, 2: 16, 4: 124}
 PREC_NAME = {1: "complex double", 2: "complex double double", 4: "complex quad double"}
 
 
+# HBM bytes per launch of the benchmark's dominant kernel from two rocprofv3
+# PMC runs (FETCH_SIZE, WRITE_SIZE), scaled by the factors a 2 GiB device copy
+# gives (profiles/eval_d_pinned_kernel_n32_k8_65536pts.md).  Valid only for the
+# kernel sources they were taken with: any change to them reports null.
+TRAFFIC = {
+    "eval_d_pinned_kernel": {
+        "bytes": 51217289 + 1107296256,   # read + write
+        "sources": {"paper_1505_00383_amd/csrc/eval.hip": "ae08e22d85b8d8a7",
+                    "paper_1505_00383_amd/csrc/ph_arith.hpp": "f4b035f2f8fac960",
+                    "paper_1505_00383_amd/csrc/system.cpp": "b5fa172bd9ad37e7"},
+    },
+}
+
+
+def traffic_of(kernel):
+    import hashlib
+    t = TRAFFIC.get(kernel)
+    if t is None:
+        return None
+    for path, sha in t["sources"].items():
+        with open(os.path.join(ROOT, path), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest()[:16] != sha:
+                return None
+    return t["bytes"]
+
+
 def flops_per_point(sysm, L):
     """Algorithmic FP64 flops of H and J at one point (cost model above),
     including the total-degree start terms x_i^{d_i} and -1."""
@@ -227,6 +253,31 @@ def tracking_extras(ph, torch):
     return out
 
 
+def profile_mode(ph, torch, mode):
+    """One run of a single workload, printing what it did (for rocprofv3)."""
+    from paper_1505_00383_amd import synth
+    if mode == "copy":
+        n = (2 << 30) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": mode, "bytes_read_per_copy": n * 8, "bytes_written_per_copy": n * 8,
+                          "copies": 3}))
+        return
+    if mode == "track_n16_qd":
+        s = synth.tracking_quadratic16()
+        res = ph.track(ph.System(s), synth.gamma_of(s), 2 ** 16, ph.track_opts(prec=4, mixed=1))
+        print(json.dumps({"mode": mode, "report": res["report"]}))
+        return
+    sysms, gammas, paths, cap = synth.batch_heterogeneous()
+    systems = [ph.System(x) for x in sysms]
+    res = ph.track_batch(systems, gammas, paths,
+                         ph.track_opts(prec=2, mixed=1, schedule=ph.SCHED_GRAPH))
+    print(json.dumps({"mode": mode, "report": res["report"]}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,6 +286,10 @@ def main():
     ap.add_argument("--prec", type=int, default=1, choices=[1, 2, 4])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--mode", default="eval", choices=["eval", "track_n16_qd", "track_batch", "copy"],
+                    help="eval: the benchmark line; the others run one workload for profiling: "
+                         "the 65536-path QD-mixed tracking, the 64-system batch, or a device "
+                         "copy of 2 GiB (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): paths and "
@@ -249,6 +304,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.mode != "eval":
+        profile_mode(ph, torch, args.mode)
+        return
     L = args.prec
     sysm = synth.eval_dense()
     gamma = synth.gamma_of(sysm)
@@ -259,6 +317,8 @@ def main():
     bpp = bytes_per_point(sysm, L)
     secs = ms * 1e-3
     achieved = fpp * npts / secs
+    kname = "eval_d_pinned_kernel" if L == 1 else f"eval_kernel<{L},8,true,true>"
+    traffic = traffic_of(kname)
     result = {
         "metric": "eval+Jacobian points/sec (paths/sec to t=1 in extras), per precision",
         "value": npts / secs,
@@ -277,8 +337,8 @@ def main():
                    "prec_limbs": L, "points": npts, "n": 32, "terms": int(sysm.n_terms),
                    "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
-                     "kernel": "eval_d_fast_kernel" if L == 1 else f"eval_kernel<{L},8,true,true>",
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic,
+                     "traffic_unit": "bytes per launch", "kernel": kname,
                      "flops_per_point": fpp, "bytes_per_point": bpp,
                      "hbm_GBps_compulsory": bpp * npts / secs / 1e9,
                      "hbm_frac_compulsory": bpp * npts / secs / PEAK_HBM},

@@ -368,11 +368,13 @@ struct PinRow {
     }
 };
 
-// Scalar copy of the part of a record the sweep needs first.
+// Scalar copy of a record: everything the sweep reads, fetched one term
+// ahead so that no scalar load is waited for inside a term.
 struct DHead {
     double cre, cim;
     int sel;
     uint32_t w[8];
+    double a[8];
 };
 
 template <int K>
@@ -384,41 +386,78 @@ __device__ __forceinline__ DHead dfast_head(const DTerm *__restrict__ r)
     h.sel = r->sel;
 #pragma unroll
     for (int l = 0; l < K; ++l) h.w[l] = r->w[l];
+#pragma unroll
+    for (int l = 0; l < K; ++l) h.a[l] = r->a[l];
     return h;
 }
 
-// One term with exactly K factors.  The head of the NEXT record (same K run)
-// is fetched once the coordinates of this term are in registers, so its
-// scalar-load latency overlaps the backward products.
-template <int K, class Row>
-__device__ __forceinline__ void dfast_sweep(const DHead &h, const DTerm *__restrict__ r,
-                                            const DTerm *__restrict__ rnext, DHead &hnext,
+// One term with exactly K factors, the first M of them with exponent >= 2
+// (the host sorts factors by exponent and groups records by (K, M)), with
+// the products of Table 6 reordered for instruction-level parallelism: all
+// coordinates and powers are read from LDS first; the suffix products
+// x_l ... x_{K-1} do not depend on the common factor and form a second
+// dependency chain beside the forward products; the M powers x^(a-1) are
+// multiplied into the coefficient by a balanced tree.  3K - 3 + M complex
+// products, the cost model's count.  The head of the NEXT record (same
+// group) is fetched once the forward chain is done.
+template <int K, int M, class Row>
+__device__ __forceinline__ void dfast_sweep(const DHead &h, const DTerm *__restrict__ rnext, DHead &hnext,
                                             const char *__restrict__ xb, int lane, C<1> cf,
                                             Row &row, C<1> &v)
 {
-    C<1> xv[K];
-    C<1> q[K];
+    C<1> xv[K], pw[M > 0 ? M : 1], sf[K], q[K];
 #pragma unroll
-    for (int l = 0; l < K; ++l) {
-        const uint32_t wl = h.w[l];
-        xv[l] = ldsc(xb, (wl & 0xffffu) * 512u, lane);
-        cf = c_mul<1>(cf, ldsc(xb, (wl >> 16) * 8u, lane));
+    for (int l = 0; l < K; ++l) xv[l] = ldsc(xb, (h.w[l] & 0xffffu) * 512u, lane);
+    // the first M factors (a >= 2) take x^(a-1) from the power table
+#pragma unroll
+    for (int l = 0; l < M; ++l) pw[l] = ldsc(xb, (h.w[l] >> 16) * 8u, lane);
+    // suffix products: sf[l] = x_l x_{l+1} ... x_{K-1}
+    sf[K - 1] = xv[K - 1];
+#pragma unroll
+    for (int l = K - 2; l >= 1; --l) sf[l] = c_mul<1>(sf[l + 1], xv[l]);
+    // common factor: c times the product of the M powers, as a balanced tree
+    if constexpr (M > 0) {
+#pragma unroll
+        for (int st = 1; st < M; st *= 2) {
+#pragma unroll
+            for (int l = 0; l + st < M; l += 2 * st) pw[l] = c_mul<1>(pw[l], pw[l + st]);
+        }
+        cf = c_mul<1>(cf, pw[0]);
     }
     q[0] = cf;
 #pragma unroll
     for (int l = 1; l < K; ++l) q[l] = c_mul<1>(q[l - 1], xv[l - 1]);
     v = c_add<1>(v, c_mul<1>(q[K - 1], xv[K - 1]));
     hnext = dfast_head<K>(rnext);
-    double ae[K];
+    row.fma((int)(h.w[K - 1] & 0xffffu), h.a[K - 1], q[K - 1]);
 #pragma unroll
-    for (int l = 0; l < K; ++l) ae[l] = r->a[l];
-    C<1> sfx = xv[K - 1];
-    row.fma((int)(h.w[K - 1] & 0xffffu), ae[K - 1], q[K - 1]);
-#pragma unroll
-    for (int l = K - 2; l >= 0; --l) {
-        row.fma((int)(h.w[l] & 0xffffu), ae[l], c_mul<1>(q[l], sfx));
-        if (l > 0) sfx = c_mul<1>(sfx, xv[l]);
+    for (int l = K - 2; l >= 0; --l) row.fma((int)(h.w[l] & 0xffffu), h.a[l], c_mul<1>(q[l], sf[l + 1]));
+}
+
+// All records of one equation, group by group: (K, M) = (1,0), (1,1), (2,0),
+// ..., (8,8), each a straight-line loop over its records.
+template <int K, int M, class Row>
+__device__ __forceinline__ void dfast_groups(const int32_t *__restrict__ run, const DTerm *__restrict__ dterm,
+                                             const char *__restrict__ xb, int lane, const C<1> &gs,
+                                             double tv, Row &row, C<1> &v)
+{
+    constexpr int g = drun_group(K, M);
+    const int s0 = run[g], s1 = run[g + 1];
+    if (s0 < s1) {
+        DHead h = dfast_head<K>(dterm + s0);
+        for (int s = s0; s < s1; ++s) {
+            const DTerm *rn = dterm + (s + 1 < s1 ? s + 1 : s);
+            const C<1> c0 = c_from<1>(h.cre, h.cim);
+            const C<1> c = (h.sel & 1) ? c_mul<1>(c0, gs) : c_mul_d<1>(c0, tv);
+            DHead hn;
+            dfast_sweep<K, M>(h, rn, hn, xb, lane, c, row, v);
+            h = hn;
+        }
     }
+    if constexpr (M < K)
+        dfast_groups<K, M + 1>(run, dterm, xb, lane, gs, tv, row, v);
+    else if constexpr (K < 8)
+        dfast_groups<K + 1, 0>(run, dterm, xb, lane, gs, tv, row, v);
 }
 
 template <class Row>
@@ -460,34 +499,13 @@ __device__ __forceinline__ void dfast_body(const EvalArgs &a, const int32_t *__r
         Row row;
         row.zero();
         C<1> v = c_zero<1>();
-        const int32_t *run = d_run + i * 10;
+        const int32_t *run = d_run + i * DRUN;
         auto coef = [&](const DTerm *r) -> C<1> {
             const C<1> c = c_from<1>(r->cre, r->cim);
-            return r->sel ? c_mul<1>(c, gs) : c_mul_d<1>(c, tv);
+            return (r->sel & 1) ? c_mul<1>(c, gs) : c_mul_d<1>(c, tv);
         };
         for (int s = run[0]; s < run[1]; ++s) v = c_add<1>(v, coef(dterm + s));
-#define PH_DFAST_RUN(K)                                                        \
-        if (run[K] < run[K + 1]) {                                             \
-            DHead h = dfast_head<K>(dterm + run[K]);                           \
-            for (int s = run[K]; s < run[K + 1]; ++s) {                        \
-                const DTerm *r = dterm + s;                                    \
-                const DTerm *rn = dterm + (s + 1 < run[K + 1] ? s + 1 : s);    \
-                const C<1> c0 = c_from<1>(h.cre, h.cim);                       \
-                const C<1> c = h.sel ? c_mul<1>(c0, gs) : c_mul_d<1>(c0, tv);  \
-                DHead hn;                                                      \
-                dfast_sweep<K>(h, r, rn, hn, xb, lane, c, row, v);             \
-                h = hn;                                                        \
-            }                                                                  \
-        }
-        PH_DFAST_RUN(1)
-        PH_DFAST_RUN(2)
-        PH_DFAST_RUN(3)
-        PH_DFAST_RUN(4)
-        PH_DFAST_RUN(5)
-        PH_DFAST_RUN(6)
-        PH_DFAST_RUN(7)
-        PH_DFAST_RUN(8)
-#undef PH_DFAST_RUN
+        dfast_groups<1, 0>(run, dterm, xb, lane, gs, tv, row, v);
         // total-degree start part: gamma (1-t) (x_i^d - 1), derivative d x_i^(d-1)
         const int d = d_deg[i];
         if (d > 0 && a.t) {

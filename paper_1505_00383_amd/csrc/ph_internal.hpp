@@ -41,9 +41,15 @@ int hip_fail(hipError_t e, const char *what);
 // and LDS byte offset of x_{j_l}^{a_l - 1} divided by 8 (bits 16..31; powers
 // x, x^2, x^3 and a row of ones are staged per point), a[l] the exponent as a
 // double (folded into the FMA that accumulates the partial).
+// Fast-path record groups: (k, m) with 0 <= m <= k <= 8, numbered k(k+1)/2 + m;
+// DRUN offsets per equation (45 groups and the end).
+constexpr int DRUN = 46;
+inline constexpr int drun_group(int k, int m) { return k * (k + 1) / 2 + m; }
+
 struct DTerm {
     double cre, cim;
-    int32_t k, sel;
+    int32_t k;
+    int32_t sel;    // bit 0: start term; bits 8..11: factors with a >= 3; 16..19: with a >= 2
     uint32_t w[8];  // 2 * variable | (LDS offset of x^(a-1), or of the ones row, / 8) << 16
     int32_t pad[2];
     double a[8];
@@ -57,8 +63,9 @@ struct DevTable {
     int32_t *d_eq_off = nullptr; // [n_eq + 1] offsets into dterm
     DTerm *dterm = nullptr;      // fast-path records (target terms, custom start terms)
     int32_t *d_deg = nullptr;    // [n_eq] total-degree start exponents (0: explicit start)
-    int32_t *d_run = nullptr;    // [n_eq][10]: records of equation i with k factors are
-                                 // d_run[i*10+k] .. d_run[i*10+k+1]-1
+    int32_t *d_run = nullptr;    // [n_eq][DRUN]: records of equation i in group g (k
+                                 // factors, m of them with a >= 2; g = drun_group(k, m))
+                                 // are d_run[i*DRUN+g] .. d_run[i*DRUN+g+1]-1
     int64_t n_terms = 0, n_fac = 0;
     int32_t *eq_off = nullptr;   // [n_eq + 1]
     int4 *tdesc = nullptr;       // [n_terms]

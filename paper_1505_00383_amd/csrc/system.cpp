@@ -137,29 +137,41 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
                 r.cim = sy.coef[size_t(t) * 8 + 4];
                 int a = sy.term_fac_off[t], b = sy.term_fac_off[t + 1];
                 r.k = b - a;
-                r.sel = sel;
-                for (int q = a; q < b; ++q) {
-                    int l = q - a, v = sy.fac_var[q], e = sy.fac_exp[q];
+                // factors by exponent, largest first: the kernel multiplies
+                // x^(a-1) from the power table for a >= 3, x itself for
+                // a = 2 and nothing for a = 1, with wave-uniform counts
+                int ord[8];
+                for (int l = 0; l < r.k; ++l) ord[l] = a + l;
+                std::stable_sort(ord, ord + r.k,
+                                 [&](int x, int y) { return sy.fac_exp[x] > sy.fac_exp[y]; });
+                int m3 = 0, m2 = 0;
+                for (int l = 0; l < r.k; ++l) {
+                    const int q = ord[l], v = sy.fac_var[q], e = sy.fac_exp[q];
                     const uint32_t poff = e == 1 ? ones_off : uint32_t(((e - 2) * nv + v) * 2 * 64 * 8);
                     r.w[l] = uint32_t(2 * v) | ((poff / 8) << 16);
                     r.a[l] = double(e);
+                    m3 += e >= 3;
+                    m2 += e >= 2;
                 }
+                r.sel = sel | (m3 << 8) | (m2 << 16);
                 dterm.push_back(r);
             }
         };
-        d_run.assign(size_t(ne) * 10, 0);
+        d_run.assign(size_t(ne) * DRUN, 0);
         for (int i = 0; i < ne; ++i) {
             const size_t first = dterm.size();
             emit_d(f, i, 0);
             if (g) emit_d(*g, i, 1);
-            // group the equation's terms by their number of factors so the
-            // kernel runs one loop per k (a stable sort keeps the term order)
+            // group the equation's terms by (k, number of factors with
+            // a >= 2) so the kernel runs one straight-line loop per group
+            // (a stable sort keeps the term order within a group)
+            auto grp = [](const DTerm &x) { return drun_group(x.k, (x.sel >> 16) & 15); };
             std::stable_sort(dterm.begin() + first, dterm.end(),
-                             [](const DTerm &x, const DTerm &y) { return x.k < y.k; });
-            for (int kk = 0; kk <= 9; ++kk) {
+                             [&](const DTerm &x, const DTerm &y) { return grp(x) < grp(y); });
+            for (int gg = 0; gg < DRUN; ++gg) {
                 size_t pos = first;
-                while (pos < dterm.size() && dterm[pos].k < kk) ++pos;
-                d_run[size_t(i) * 10 + kk] = int32_t(pos);
+                while (pos < dterm.size() && grp(dterm[pos]) < gg) ++pos;
+                d_run[size_t(i) * DRUN + gg] = int32_t(pos);
             }
             d_eq_off[i + 1] = int32_t(dterm.size());
             d_deg[i] = (!g && ne == nv) ? f.deg[i] : 0;
