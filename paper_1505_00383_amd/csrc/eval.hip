@@ -368,6 +368,43 @@ struct PinRow {
     }
 };
 
+// The row of a system with at most 16 unknowns, pinned in v[64:127] (real
+// parts of columns 0..15 in v[64:95], imaginary parts in v[96:127]) for a
+// kernel compiled with a 64-register budget: 128 registers in all, so four
+// waves fit each SIMD instead of two.  Same rules as PinRow.
+#define PH_PIN16_CLOBBERS "v64","v65","v66","v67","v68","v69","v70","v71","v72","v73","v74","v75","v76","v77","v78","v79","v80","v81","v82","v83","v84","v85","v86","v87","v88","v89","v90","v91","v92","v93","v94","v95","v96","v97","v98","v99","v100","v101","v102","v103","v104","v105","v106","v107","v108","v109","v110","v111","v112","v113","v114","v115","v116","v117","v118","v119","v120","v121","v122","v123","v124","v125","v126","v127"
+struct PinRow16 {
+    __device__ __forceinline__ void zero()
+    {
+        asm volatile("v_mov_b64 v[64:65], 0\n\tv_mov_b64 v[66:67], 0\n\tv_mov_b64 v[68:69], 0\n\tv_mov_b64 v[70:71], 0\n\tv_mov_b64 v[72:73], 0\n\tv_mov_b64 v[74:75], 0\n\tv_mov_b64 v[76:77], 0\n\tv_mov_b64 v[78:79], 0\n\tv_mov_b64 v[80:81], 0\n\tv_mov_b64 v[82:83], 0\n\tv_mov_b64 v[84:85], 0\n\tv_mov_b64 v[86:87], 0\n\tv_mov_b64 v[88:89], 0\n\tv_mov_b64 v[90:91], 0\n\tv_mov_b64 v[92:93], 0\n\tv_mov_b64 v[94:95], 0\n\tv_mov_b64 v[96:97], 0\n\tv_mov_b64 v[98:99], 0\n\tv_mov_b64 v[100:101], 0\n\tv_mov_b64 v[102:103], 0\n\tv_mov_b64 v[104:105], 0\n\tv_mov_b64 v[106:107], 0\n\tv_mov_b64 v[108:109], 0\n\tv_mov_b64 v[110:111], 0\n\tv_mov_b64 v[112:113], 0\n\tv_mov_b64 v[114:115], 0\n\tv_mov_b64 v[116:117], 0\n\tv_mov_b64 v[118:119], 0\n\tv_mov_b64 v[120:121], 0\n\tv_mov_b64 v[122:123], 0\n\tv_mov_b64 v[124:125], 0\n\tv_mov_b64 v[126:127], 0" ::: PH_PIN16_CLOBBERS);
+    }
+    __device__ __forceinline__ void fma(int j2, double e, const C<1> &d)
+    {
+        asm volatile("s_set_gpr_idx_on %0, gpr_idx(SRC2,DST)\n\t"
+                     "v_fma_f64 v[64:65], %1, %2, v[64:65]\n\t"
+                     "v_fma_f64 v[96:97], %1, %3, v[96:97]\n\t"
+                     "s_set_gpr_idx_off"
+                     :
+                     : "s"(j2), "s"(e), "v"(d.re.v[0]), "v"(d.im.v[0])
+                     : PH_PIN16_CLOBBERS);
+    }
+    __device__ __forceinline__ void get(int j, double &re, double &im)
+    {
+        unsigned rl, rh, il, ih;
+        asm volatile("s_set_gpr_idx_on %4, gpr_idx(SRC0)\n\t"
+                     "v_mov_b32 %0, v64\n\t"
+                     "v_mov_b32 %1, v65\n\t"
+                     "v_mov_b32 %2, v96\n\t"
+                     "v_mov_b32 %3, v97\n\t"
+                     "s_set_gpr_idx_off"
+                     : "=v"(rl), "=v"(rh), "=v"(il), "=v"(ih)
+                     : "s"(2 * j)
+                     : PH_PIN16_CLOBBERS);
+        re = __builtin_bit_cast(double, ((unsigned long long)rh << 32) | rl);
+        im = __builtin_bit_cast(double, ((unsigned long long)ih << 32) | il);
+    }
+};
+
 // Scalar copy of a record: everything the sweep reads, fetched one term
 // ahead so that no scalar load is waited for inside a term.
 struct DHead {
@@ -436,7 +473,7 @@ __device__ __forceinline__ void dfast_sweep(const DHead &h, const DTerm *__restr
 
 // All records of one equation, group by group: (K, M) = (1,0), (1,1), (2,0),
 // ..., (8,8), each a straight-line loop over its records.
-template <int K, int M, class Row>
+template <int K, int M, int KF, class Row>
 __device__ __forceinline__ void dfast_groups(const int32_t *__restrict__ run, const DTerm *__restrict__ dterm,
                                              const char *__restrict__ xb, int lane, const C<1> &gs,
                                              double tv, Row &row, C<1> &v)
@@ -455,12 +492,14 @@ __device__ __forceinline__ void dfast_groups(const int32_t *__restrict__ run, co
         }
     }
     if constexpr (M < K)
-        dfast_groups<K, M + 1>(run, dterm, xb, lane, gs, tv, row, v);
-    else if constexpr (K < 8)
-        dfast_groups<K + 1, 0>(run, dterm, xb, lane, gs, tv, row, v);
+        dfast_groups<K, M + 1, KF>(run, dterm, xb, lane, gs, tv, row, v);
+    else if constexpr (K < KF)
+        dfast_groups<K + 1, 0, KF>(run, dterm, xb, lane, gs, tv, row, v);
 }
 
-template <class Row>
+// KF: largest number of factors per term the kernel handles; NC: largest
+// number of unknowns (Jacobian columns held in the row).
+template <class Row, int KF, int NC>
 __device__ __forceinline__ void dfast_body(const EvalArgs &a, const int32_t *__restrict__ d_run,
                                            const DTerm *__restrict__ dterm,
                                            const int32_t *__restrict__ d_deg, int planes)
@@ -505,7 +544,7 @@ __device__ __forceinline__ void dfast_body(const EvalArgs &a, const int32_t *__r
             return (r->sel & 1) ? c_mul<1>(c, gs) : c_mul_d<1>(c, tv);
         };
         for (int s = run[0]; s < run[1]; ++s) v = c_add<1>(v, coef(dterm + s));
-        dfast_groups<1, 0>(run, dterm, xb, lane, gs, tv, row, v);
+        dfast_groups<1, 0, KF>(run, dterm, xb, lane, gs, tv, row, v);
         // total-degree start part: gamma (1-t) (x_i^d - 1), derivative d x_i^(d-1)
         const int d = d_deg[i];
         if (d > 0 && a.t) {
@@ -523,7 +562,7 @@ __device__ __forceinline__ void dfast_body(const EvalArgs &a, const int32_t *__r
             a.val[((int64_t)(i * 2 + 1)) * a.ld + p] = v.im.v[0];
             double *jr = a.jac + (int64_t)i * nv * 2 * a.ld + p;
 #pragma unroll
-            for (int j = 0; j < 32; ++j) {
+            for (int j = 0; j < NC; ++j) {
                 if (j < nv) {
                     double re, im;
                     row.get(j, re, im);
@@ -539,7 +578,7 @@ __global__ void __launch_bounds__(512) eval_d_fast_kernel(EvalArgs a, const int3
                                                           const DTerm *__restrict__ dterm,
                                                           const int32_t *__restrict__ d_deg, int planes)
 {
-    dfast_body<VecRow>(a, d_run, dterm, d_deg, planes);
+    dfast_body<VecRow, 8, 32>(a, d_run, dterm, d_deg, planes);
 }
 
 // The same with the row pinned in v[128:255] (PinRow); everything else of
@@ -548,7 +587,16 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_num_vgpr(128)))
 eval_d_pinned_kernel(EvalArgs a, const int32_t *__restrict__ d_run, const DTerm *__restrict__ dterm,
                      const int32_t *__restrict__ d_deg, int planes)
 {
-    dfast_body<PinRow>(a, d_run, dterm, d_deg, planes);
+    dfast_body<PinRow, 8, 32>(a, d_run, dterm, d_deg, planes);
+}
+
+// Systems with n <= 16 and at most two factors per term (PinRow16): four
+// waves per SIMD for the evaluations that are bound by HBM traffic.
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_num_vgpr(64)))
+eval_d_pinned16_kernel(EvalArgs a, const int32_t *__restrict__ d_run, const DTerm *__restrict__ dterm,
+                       const int32_t *__restrict__ d_deg, int planes)
+{
+    dfast_body<PinRow16, 2, 16>(a, d_run, dterm, d_deg, planes);
 }
 
 template <int L, int KMAX, bool XLDS, bool JAC>
@@ -630,7 +678,10 @@ int eval_launch(const DevTable &tab, const double gamma[2], int prec, int64_t np
     const size_t lds = (size_t)tab.n_var * 2 * prec * 64 * sizeof(double);
     if (kernel == 3 || kernel == 4) {
         const size_t ldsf = ((size_t)tab.dfast_planes * tab.n_var * 2 + 2) * 64 * sizeof(double);
-        if (kernel == 3)
+        if (kernel == 3 && tab.n_var <= 16 && tab.kmax <= 2)
+            hipLaunchKernelGGL(eval_d_pinned16_kernel, grid, dim3(64 * W), ldsf, st, a, tab.d_run,
+                               tab.dterm, tab.d_deg, tab.dfast_planes);
+        else if (kernel == 3)
             hipLaunchKernelGGL(eval_d_pinned_kernel, grid, dim3(64 * W), ldsf, st, a, tab.d_run,
                                tab.dterm, tab.d_deg, tab.dfast_planes);
         else

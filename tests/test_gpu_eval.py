@@ -204,3 +204,31 @@ def test_start_solutions_match_oracle(L):
     xs2 = ph.start_solutions(S, L, 100, 50)
     torch.cuda.synchronize()
     assert np.array_equal(ph.from_soa(xs2, 50, (n, 2, L)), X[100:150])
+
+
+def test_eval_hbm_bound_workload_sampled():
+    """n = 16, degree 2 (at most two factors per term, the 16-column pinned
+    kernel), 2^20 points as in the benchmark's HBM-bound launch; the oracle
+    recomputes sampled points, and a ragged 64-point tail is checked in full."""
+    import torch
+    s = synth.tracking_quadratic16()
+    g = synth.gamma_of(s)
+    npts = 1 << 20
+    rng = np.random.Generator(np.random.PCG64(synth.SEED_BASE + 3))
+    x, t = synth.torus_points(s, npts, 1, rng)
+    S = ph.System(s)
+    xs = ph.to_soa(x)
+    tt = torch.as_tensor(t, dtype=torch.float64).cuda()
+    val, jm = ph.eval_jac(S, xs, npts, 1, tt, g)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(jm).all())
+    idx = np.unique(np.concatenate([[0, 1, 63, 64, npts - 1],
+                                    np.random.default_rng(21).integers(0, npts, 24)]))
+    it = torch.as_tensor(idx, device="cuda")
+    v = val[:, it].T.contiguous().cpu().numpy().reshape(len(idx), 16, 2, 1)
+    j = jm[:, it].T.contiguous().cpu().numpy().reshape(len(idx), 16, 16, 2, 1)
+    ov, oj, sv, sj = oracle.eval_homotopy(s, 1, x[idx], t[idx], g)
+    ev, ej = scaled_error(v, ov, sv), scaled_error(j, oj, sj)
+    print(f"[gpu] n16 d2 2^20 points: val_err/S={ev:.2e} jac_err/S={ej:.2e}", flush=True)
+    assert ev <= TOL[1] and ej <= TOL[1]
+    _check(s, 1, x[:64 * 3 + 17], t[:64 * 3 + 17], g)
