@@ -225,6 +225,68 @@ def hbm_extra(ph, torch, steps):
             "hbm_frac_compulsory": bpp * npts / (ms * 1e-3) / PEAK_HBM, "finite": ok}
 
 
+# The paper's own speedups of its GPU evaluation over one CPU core (Tables
+# of Section 4, a Tesla K20C against one core of a Xeon E5-2670): context for
+# the stand-ins of the same shape, not a target.
+PAPER_EVAL_SPEEDUP = {"cyclic10": {1: 13.50, 2: 77.47, 4: 99.44},
+                      "nash8": {1: 13.97, 2: 81.75, 4: 95.07},
+                      "pieri44": {1: 14.67, 2: 81.60, 4: 89.79}}
+
+
+def unfused_extra(ph, torch, S, sysm, gamma, steps):
+    """The paper's three-kernel design (coeff / mon / sum with the products
+    stored in device memory) against the fused kernel on the benchmark
+    workload, D and DD; the bytes its intermediate arrays move per point."""
+    out = {}
+    npts = 65536
+    slots = sum(int(sysm.term_fac_off[s + 1] - sysm.term_fac_off[s]) + 1 for s in range(sysm.n_terms))
+    slots += 3 * sysm.n_eq                   # start terms x_i^d (2 slots) and -1 (1 slot)
+    terms = sysm.n_terms + 2 * sysm.n_eq
+    for L in (1, 2):
+        ph.eval_set_config(S, L, ph.EVAL_UNFUSED)
+        ms, ok, _, _ = time_eval(ph, torch, S, sysm, L, npts, steps, 1, gamma)
+        ph.eval_set_config(S, L)
+        fused, _, _, _ = time_eval(ph, torch, S, sysm, L, npts, steps, 1, gamma)
+        inter = 16 * L * (2 * terms + 2 * slots)   # cff written + read, slots written + read
+        out[PREC_NAME[L]] = {"unfused_ms": ms, "fused_ms": fused, "fusion_speedup": ms / fused,
+                             "intermediate_bytes_per_point": inter,
+                             "unfused_intermediate_GBps": inter * npts / (ms * 1e-3) / 1e9,
+                             "finite": ok}
+    return out
+
+
+def paper_shaped_extra(ph, torch, cpu_seconds=1.0):
+    """Evaluation of the stand-ins shaped like the paper's benchmark systems at
+    as many points as the paper has paths, in D/DD/QD, beside the oracle on
+    ONE host core (the paper's convention) on a bounded sample."""
+    import oracle
+    from paper_1505_00383_amd import synth
+    out = {}
+    for name, make in synth.SHAPED.items():
+        s = make()
+        g = synth.gamma_of(s)
+        S = ph.System(s)
+        npts = int(s.meta["paths"])
+        row = {"n": s.n_var, "monomials": s.n_terms, "points": npts}
+        for L in (1, 2, 4):
+            rng = np.random.Generator(np.random.PCG64(synth.SEED_BASE + 20 + L))
+            ms, ok, x, t = time_eval(ph, torch, S, s, L, npts, 5, 1, g, rng)
+            t0 = time.perf_counter()
+            oracle.eval_homotopy(s, L, x[:1], t[:1], g, scales=False)
+            one = time.perf_counter() - t0
+            m = max(1, min(64, int(cpu_seconds / max(one, 1e-6))))
+            t0 = time.perf_counter()
+            oracle.eval_homotopy(s, L, x[:m], t[:m], g, scales=False)
+            cpu = m / (time.perf_counter() - t0)
+            gpu = npts / (ms * 1e-3)
+            row[PREC_NAME[L]] = {"gpu_points_per_s": gpu, "ms": ms, "finite": ok,
+                                 "oracle_1core_points_per_s": cpu, "oracle_sample_points": m,
+                                 "speedup_vs_1core_oracle": gpu / cpu,
+                                 "paper_speedup_k20c_vs_1core_context": PAPER_EVAL_SPEEDUP[name][L]}
+        out[name] = row
+    return out
+
+
 def tracking_extras(ph, torch):
     from paper_1505_00383_amd import synth
     out = {}
@@ -355,8 +417,11 @@ def main():
                                         "fp64_frac": f2 * npts / (ms2 * 1e-3) / PEAK_FP64,
                                         "finite": ok2}
         extras["eval_n16_d2_hbm_1M_points_double"] = hbm_extra(ph, torch, max(3, args.steps // 4))
+        extras["unfused_three_kernel_ablation"] = unfused_extra(ph, torch, S, sysm, gamma, 5)
         extras.update(tracking_extras(ph, torch))
         extras["track_batch64_dd_mixed"] = batch_extra(ph, torch)
+        if not args.no_cpu_baseline:
+            extras["paper_shaped_eval"] = paper_shaped_extra(ph, torch)
         result["extras"] = extras
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(sysm, L, x, t, gamma)

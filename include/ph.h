@@ -124,7 +124,12 @@ int ph_eval_jac(const ph_system *target, const ph_system *start, const double ga
  * (target, start, prec): kernel 0 automatic, 1 general (Jacobian row
  * accumulated in the output), 2 register-resident row (double, n_var <= 32),
  * 3 double fast path (n_var <= 32, <= 8 factors per term, exponents <= 4)
- * with the row in pinned registers, 4 the same with a compiler-held row;
+ * with the row in pinned registers, 4 the same with a compiler-held row,
+ * 5 the paper's unfused design (coeff, mon and sum kernels with the
+ * coefficients and the k + 1 products of every term and point stored in
+ * device memory between them; an ablation of the fused kernels, caching its
+ * intermediate arrays -- (terms + slots) * 16 * prec bytes per point -- in
+ * the system handle; waves and groups are ignored);
  * waves = waves per workgroup sharing one 64-point tile (1..8, 0 default);
  * groups = equation groups per tile (power of two, 0 default).  All zero
  * clears the setting.  Host-only; PH_EINVAL on bad values.  A kernel that

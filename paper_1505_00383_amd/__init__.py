@@ -28,7 +28,7 @@ EXPORTED = ["ph_system_create", "ph_system_destroy", "ph_system_info", "ph_syste
             "ph_eval_autotune", "ph_track_autotune"]
 
 # ph_eval_set_config kernels
-EVAL_AUTO, EVAL_GENERAL, EVAL_REGROW, EVAL_FAST, EVAL_FAST_VECROW = 0, 1, 2, 3, 4
+EVAL_AUTO, EVAL_GENERAL, EVAL_REGROW, EVAL_FAST, EVAL_FAST_VECROW, EVAL_UNFUSED = 0, 1, 2, 3, 4, 5
 
 
 class TrackOpts(ctypes.Structure):

@@ -656,6 +656,7 @@ int eval_launch(const DevTable &tab, const double gamma[2], int prec, int64_t np
     const bool can_fast = prec == 1 && wj && tab.n_var <= 32 && tab.dfast;
     const bool can_reg = prec == 1 && wj && tab.n_var <= 32 && tab.kmax <= 16;
     int kernel = cfg ? cfg->kernel : 0;
+    if (kernel == 5) return unfused_launch(tab, gamma, prec, npts, t, x, ld, val, jac, st);
     if ((kernel == 3 || kernel == 4) && !can_fast)
         return fail(PH_EUNSUPPORTED, "fast path not available for this system");
     if (kernel == 2 && !can_reg) return fail(PH_EUNSUPPORTED, "register-row kernel not available");
@@ -786,8 +787,8 @@ extern "C" int ph_eval_set_config(ph_system *target, const ph_system *start, int
 {
     if (!target) return fail(PH_EINVAL, "null target system");
     if (prec != 1 && prec != 2 && prec != 4) return fail(PH_EINVAL, "prec must be 1, 2 or 4");
-    if (kernel < 0 || kernel > 4 || waves < 0 || waves > 8 || groups < 0)
-        return fail(PH_EINVAL, "kernel must be 0..4, waves 0..8, groups >= 0");
+    if (kernel < 0 || kernel > 5 || waves < 0 || waves > 8 || groups < 0)
+        return fail(PH_EINVAL, "kernel must be 0..5, waves 0..8, groups >= 0");
     std::lock_guard<std::mutex> lk(target->mu);
     if (kernel == 0 && waves == 0 && groups == 0)
         target->eval_cfg.erase({start, prec});

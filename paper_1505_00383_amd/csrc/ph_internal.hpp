@@ -37,10 +37,11 @@ int hip_fail(hipError_t e, const char *what);
 // on its own point (Section 3: all threads of a block evaluate the same
 // monomial at different points).
 // Term record of the complex-double fast path: everything one term needs in
-// one 128-byte block read through scalar loads.  w[l] = variable (bits 0..15)
-// and LDS byte offset of x_{j_l}^{a_l - 1} divided by 8 (bits 16..31; powers
-// x, x^2, x^3 and a row of ones are staged per point), a[l] the exponent as a
-// double (folded into the FMA that accumulates the partial).
+// one 128-byte block read through scalar loads.  w[l] = 2 * variable (bits
+// 0..15, the register index of its Jacobian column) and LDS byte offset of
+// x_{j_l}^{a_l - 1} divided by 8 (bits 16..31; powers x, x^2, x^3 and a row
+// of ones are staged per point), a[l] the exponent as a double (folded into
+// the FMA that accumulates the partial).
 // Fast-path record groups: (k, m) with 0 <= m <= k <= 8, numbered k(k+1)/2 + m;
 // DRUN offsets per equation (45 groups and the end).
 constexpr int DRUN = 46;
@@ -73,13 +74,21 @@ struct DevTable {
     double *coef = nullptr;      // [n_terms][2][4] limbs
     int32_t *zc_off = nullptr;   // [n_eq + 1] columns of each row no term touches
     int32_t *zc = nullptr;
+    // the paper's unfused three-kernel design (coeff, mon, sum; an ablation):
+    int64_t u_slots = 0;         // monomial slots: value and k partials per term
+    int32_t *u_slot = nullptr;   // [n_terms] first slot of each term
+    int32_t *u_off = nullptr;    // [n_eq * (1 + n_var) + 1] slots summed into each output
+    int32_t *u_list = nullptr;   //   entry: H_i (entries 0..n_eq-1), then J_ij row-major
     void *block = nullptr;       // single device allocation holding all of the above
+    void *u_scratch = nullptr;   // grow-only intermediate arrays of the unfused design
+    size_t u_scratch_bytes = 0;
 };
 
 // Kernel choice and tiling of one evaluation: kernel 0 automatic, 1 general
 // (Jacobian row accumulated in the output), 2 register row (double, n <= 32),
 // 3 double fast path with the row pinned in the upper registers, 4 the same
-// with a compiler-held row; W waves per workgroup, G equation groups (0: default).
+// with a compiler-held row, 5 the unfused coeff / mon / sum kernels; W waves
+// per workgroup, G equation groups (0: default).
 struct EvalCfg {
     int kernel = 0, W = 0, G = 0;
 };
@@ -111,6 +120,10 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out);
 void free_table(DevTable &t);
 // Table for (target, start), built on first use and cached in the target.
 int get_table(const ph_system *target, const ph_system *start, const DevTable **out);
+// The unfused three-kernel evaluation (kernel choice 5).
+int unfused_launch(const DevTable &tab, const double gamma[2], int prec, int64_t npts,
+                   const double *t, const double *x, int64_t ld, double *val, double *jac,
+                   hipStream_t st);
 // Evaluation launch with an explicit configuration (cfg == NULL: defaults).
 int eval_launch(const DevTable &tab, const double gamma[2], int prec, int64_t npts,
                 const double *t, const double *x, int64_t ld, double *val, double *jac,

@@ -29,6 +29,7 @@ int hip_fail(hipError_t e, const char *what)
 void free_table(DevTable &t)
 {
     if (t.block) (void)hipFree(t.block);
+    if (t.u_scratch) (void)hipFree(t.u_scratch);
     t = DevTable{};
 }
 
@@ -179,6 +180,32 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
         if (dterm.empty()) dterm.push_back(DTerm{});
     }
 
+    // ---- the unfused design: one slot per term value and per partial,
+    // and for every output entry the list of slots summed into it ----
+    std::vector<int32_t> u_slot(tdesc.size()), u_off(size_t(ne) * (1 + nv) + 1, 0), u_list;
+    {
+        std::vector<std::vector<int32_t>> lists(size_t(ne) * (1 + nv));
+        int64_t slot = 0;
+        for (int i = 0; i < ne; ++i) {
+            for (int tt = eq_off[i]; tt < eq_off[i + 1]; ++tt) {
+                u_slot[tt] = int32_t(slot);
+                lists[i].push_back(int32_t(slot));
+                for (int l = 0; l < tdesc[tt].x; ++l) {
+                    const int v = fac_var(fac[tdesc[tt].y + l]);
+                    lists[size_t(ne) + size_t(i) * nv + v].push_back(int32_t(slot + 1 + l));
+                }
+                slot += 1 + tdesc[tt].x;
+            }
+        }
+        out.u_slots = slot;
+        for (size_t e = 0; e < lists.size(); ++e) {
+            u_list.insert(u_list.end(), lists[e].begin(), lists[e].end());
+            u_off[e + 1] = int32_t(u_list.size());
+        }
+        if (u_slot.empty()) u_slot.push_back(0);
+        if (u_list.empty()) u_list.push_back(0);
+    }
+
     if (tdesc.empty()) {  // keep every pointer valid
         tdesc.push_back(int4{0, 0, 0, 0});
         coef.resize(8, 0.0);
@@ -196,7 +223,10 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
     size_t o_dt = o_deo + align256(d_eq_off.size() * 4);
     size_t o_dd = o_dt + align256(dterm.size() * sizeof(DTerm));
     size_t o_dr = o_dd + align256(d_deg.size() * 4);
-    size_t total = o_dr + align256(d_run.size() * 4);
+    size_t o_us = o_dr + align256(d_run.size() * 4);
+    size_t o_uo = o_us + align256(u_slot.size() * 4);
+    size_t o_ul = o_uo + align256(u_off.size() * 4);
+    size_t total = o_ul + align256(u_list.size() * 4);
     std::vector<char> host(total, 0);
     std::memcpy(host.data() + o_eq, eq_off.data(), eq_off.size() * 4);
     std::memcpy(host.data() + o_td, tdesc.data(), tdesc.size() * sizeof(int4));
@@ -208,6 +238,9 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
     if (!dterm.empty()) std::memcpy(host.data() + o_dt, dterm.data(), dterm.size() * sizeof(DTerm));
     std::memcpy(host.data() + o_dd, d_deg.data(), d_deg.size() * 4);
     std::memcpy(host.data() + o_dr, d_run.data(), d_run.size() * 4);
+    std::memcpy(host.data() + o_us, u_slot.data(), u_slot.size() * 4);
+    std::memcpy(host.data() + o_uo, u_off.data(), u_off.size() * 4);
+    std::memcpy(host.data() + o_ul, u_list.data(), u_list.size() * 4);
     char *dev = nullptr;
     PH_HIP(hipMalloc(&dev, total));
     hipError_t e = hipMemcpy(dev, host.data(), total, hipMemcpyHostToDevice);
@@ -234,6 +267,9 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
     out.dterm = reinterpret_cast<DTerm *>(dev + o_dt);
     out.d_deg = reinterpret_cast<int32_t *>(dev + o_dd);
     out.d_run = reinterpret_cast<int32_t *>(dev + o_dr);
+    out.u_slot = reinterpret_cast<int32_t *>(dev + o_us);
+    out.u_off = reinterpret_cast<int32_t *>(dev + o_uo);
+    out.u_list = reinterpret_cast<int32_t *>(dev + o_ul);
     return PH_OK;
 }
 

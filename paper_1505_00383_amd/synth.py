@@ -265,5 +265,68 @@ def batch_heterogeneous(seed: int = SEED_BASE + 4, nsys: int = 64, target_paths:
     return systems, gammas, paths, cap
 
 
+# ---------------------------------------------------------------------------
+# Stand-ins shaped like the paper's three benchmark systems (Section 4 lists
+# their dimensions, monomial counts and degrees).  Only the shape is taken:
+# the supports are drawn at random (multilinear monomials over random
+# variable subsets) and every coefficient is a random unit complex number, so
+# none of the actual systems is reproduced.
+# ---------------------------------------------------------------------------
+
+def _subsets(n, sizes):
+    return [c for d in sizes for c in itertools.combinations(range(n), d)]
+
+
+def _multilinear_equation(rng, n, n_terms, sizes, must=()):
+    """``n_terms`` distinct multilinear monomials over n unknowns, drawn without
+    replacement from the variable subsets whose size is in ``sizes``; one of
+    each size in ``must`` first."""
+    pool = _subsets(n, sizes)
+    picked = []
+    for d in must:
+        cands = [i for i, c in enumerate(pool) if len(c) == d and i not in picked]
+        picked.append(cands[int(rng.integers(0, len(cands)))])
+    rest = [i for i in range(len(pool)) if i not in set(picked)]
+    picked += [rest[int(j)] for j in rng.choice(len(rest), size=n_terms - len(picked), replace=False)]
+    return [(unit_complex(rng), {v: 1 for v in pool[i]}) for i in picked]
+
+
+def shaped_cyclic10(seed: int = SEED_BASE + 10):
+    """n = 10; equation k (k = 1..9) has 10 monomials of degree k, the last
+    equation two terms (a monomial in all 10 unknowns and a constant): 92
+    monomials, the shape of the cyclic 10-roots system."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = 10
+    eqs = [_multilinear_equation(rng, n, 10, [k]) for k in range(1, n)]
+    eqs.append([(unit_complex(rng), {v: 1 for v in range(n)}), (unit_complex(rng), {})])
+    gamma = unit_complex(rng)
+    return system_from_terms(n, eqs, name="shaped-cyclic10", meta={"gamma": gamma, "paths": 34940})
+
+
+def shaped_nash8(seed: int = SEED_BASE + 11):
+    """n = 8; every equation has 130 multilinear monomials of degrees 1..7
+    (every degree present; 1040 monomials in all), the shape of the 8-player
+    Nash equilibrium system."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = 8
+    eqs = [_multilinear_equation(rng, n, 130, range(1, 8), must=range(1, 8)) for _ in range(n)]
+    gamma = unit_complex(rng)
+    return system_from_terms(n, eqs, name="shaped-nash8", meta={"gamma": gamma, "paths": 14833})
+
+
+def shaped_pieri44(seed: int = SEED_BASE + 12):
+    """n = 16; every equation has 246 multilinear monomials of degree at most
+    4, at least one of degree 4 (3936 in all), the shape of the Pieri
+    hypersurface system with four-planes."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = 16
+    eqs = [_multilinear_equation(rng, n, 246, range(1, 5), must=(4,)) for _ in range(n)]
+    gamma = unit_complex(rng)
+    return system_from_terms(n, eqs, name="shaped-pieri44", meta={"gamma": gamma, "paths": 24024})
+
+
+SHAPED = {"cyclic10": shaped_cyclic10, "nash8": shaped_nash8, "pieri44": shaped_pieri44}
+
+
 def gamma_of(sysm: System) -> complex:
     return complex(sysm.meta["gamma"])

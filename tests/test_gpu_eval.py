@@ -232,3 +232,28 @@ def test_eval_hbm_bound_workload_sampled():
     print(f"[gpu] n16 d2 2^20 points: val_err/S={ev:.2e} jac_err/S={ej:.2e}", flush=True)
     assert ev <= TOL[1] and ej <= TOL[1]
     _check(s, 1, x[:64 * 3 + 17], t[:64 * 3 + 17], g)
+
+
+@pytest.mark.parametrize("name", ["cyclic10", "nash8", "pieri44"])
+@pytest.mark.parametrize("L", LIMBS)
+def test_eval_paper_shaped_stand_ins(name, L):
+    """Systems with the dimensions, monomial counts and degrees of the paper's
+    three benchmark systems (multilinear, k up to 10): 300 points (a ragged
+    tile), sampled points against the oracle."""
+    import torch
+    s = synth.SHAPED[name]()
+    g = synth.gamma_of(s)
+    rng = np.random.default_rng(30 + L)
+    npts = 300
+    x, t = synth.torus_points(s, npts, L, rng)
+    S = ph.System(s)
+    val, jm = ph.eval_jac(S, ph.to_soa(x), npts, L, torch.as_tensor(t, dtype=torch.float64).cuda(), g)
+    torch.cuda.synchronize()
+    idx = np.array([0, 63, 64, 201, npts - 1])
+    it = torch.as_tensor(idx, device="cuda")
+    v = val[:, it].T.contiguous().cpu().numpy().reshape(len(idx), s.n_eq, 2, L)
+    j = jm[:, it].T.contiguous().cpu().numpy().reshape(len(idx), s.n_eq, s.n_var, 2, L)
+    ov, oj, sv, sj = oracle.eval_homotopy(s, L, x[idx], t[idx], g)
+    ev, ej = scaled_error(v, ov, sv), scaled_error(j, oj, sj)
+    print(f"[gpu] shaped {name} L={L}: val_err/S={ev:.2e} jac_err/S={ej:.2e}", flush=True)
+    assert ev <= TOL[L] and ej <= TOL[L]

@@ -43,21 +43,44 @@ def test_every_configuration_matches_oracle(L):
     g = synth.gamma_of(s)
     ov, oj, sv, sj = oracle.eval_homotopy(s, L, x, t, g)
     S = ph.System(s)
-    kernels = [ph.EVAL_GENERAL] + ([ph.EVAL_REGROW, ph.EVAL_FAST, ph.EVAL_FAST_VECROW]
-                                  if L == 1 else [])
+    kernels = [ph.EVAL_GENERAL, ph.EVAL_UNFUSED] + ([ph.EVAL_REGROW, ph.EVAL_FAST, ph.EVAL_FAST_VECROW]
+                                                   if L == 1 else [])
     worst = 0.0
     for k in kernels:
-        for W in (1, 2, 4, 8):
-            for G in (1, 2, 4):
-                ph.eval_set_config(S, L, k, W, G)
-                v, j = _eval(S, s, L, x, t, g)
-                e = max(scaled_error(v, ov, sv), scaled_error(j, oj, sj))
-                worst = max(worst, e)
-                assert e <= TOL[L], (k, W, G, e)
+        tilings = [(0, 0)] if k == ph.EVAL_UNFUSED else [(W, G) for W in (1, 2, 4, 8) for G in (1, 2, 4)]
+        for W, G in tilings:
+            ph.eval_set_config(S, L, k, W, G)
+            v, j = _eval(S, s, L, x, t, g)
+            e = max(scaled_error(v, ov, sv), scaled_error(j, oj, sj))
+            worst = max(worst, e)
+            assert e <= TOL[L], (k, W, G, e)
     ph.eval_set_config(S, L)   # back to automatic
     v, j = _eval(S, s, L, x, t, g)
     assert max(scaled_error(v, ov, sv), scaled_error(j, oj, sj)) <= TOL[L]
     print(f"[gpu] L={L} configs ok, worst err/S={worst:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_unfused_design_long_terms_and_values_only(L):
+    """The paper's three-kernel design on a system with terms of 10 factors
+    (the cyclic10-shaped stand-in), with and without the Jacobian, and on a
+    second, larger call that regrows its intermediate arrays."""
+    import torch
+    s = synth.SHAPED["cyclic10"]()
+    g = synth.gamma_of(s)
+    S = ph.System(s)
+    ph.eval_set_config(S, L, ph.EVAL_UNFUSED)
+    for npts in (70, 200):
+        rng = np.random.default_rng(40 + npts)
+        x, t = synth.torus_points(s, npts, L, rng)
+        ov, oj, sv, sj = oracle.eval_homotopy(s, L, x, t, g)
+        v, j = _eval(S, s, L, x, t, g)
+        assert max(scaled_error(v, ov, sv), scaled_error(j, oj, sj)) <= TOL[L]
+        val, none = ph.eval_jac(S, ph.to_soa(x), npts, L, torch.as_tensor(t, dtype=torch.float64).cuda(),
+                                g, want_jac=False)
+        torch.cuda.synchronize()
+        assert none is None
+        assert scaled_error(ph.from_soa(val, npts, (s.n_eq, 2, L)), ov, sv) <= TOL[L]
 
 
 def test_inapplicable_kernel_is_refused():
