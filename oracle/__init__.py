@@ -74,6 +74,7 @@ def lib():
         L.ora_start_solution.argtypes = [i32, i32, P, i64, P]
         L.ora_start_solution.restype = i32
         L.ora_track_path.argtypes = [i32, P, i32, i32, P, P, P, P, P, P, P, P, P, P, P, P]
+        L.ora_extrapolate.argtypes = [i32, i32, i32, P, P, ctypes.c_double, P]
         L.ora_track_path.restype = i32
         _lib = L
     return _lib
@@ -239,6 +240,17 @@ def _copts(o: Opts) -> _COpts:
     if d["polish_tol"] < 0:
         d["polish_tol"] = 8.0 * unit_roundoff(o.prec)
     return _COpts(**d)
+
+
+def extrapolate(L: int, T, X, t1: float):
+    """Predictor of order m = len(T) - 1 (Section 2): the interpolant of the
+    points (T[j], X[j]) evaluated at t1.  X: [m+1, n, 2, L]."""
+    T = _c(T, np.float64)
+    X = _c(X, np.float64)
+    m, n = len(T) - 1, X.shape[1]
+    out = np.zeros((n, 2, L))
+    lib().ora_extrapolate(L, m, n, _p(T), _p(X), float(t1), _p(out))
+    return out
 
 
 def track_path(s, gamma, x0, opts: Opts):

@@ -745,9 +745,63 @@ static int newton_step(int L, int mixed, const sysv *f, const sysv *g, const int
 }
 
 /*
+ * Predictor of order m >= 2 (Section 2: an extrapolation applied to each
+ * coordinate separately; a fourth-order predictor uses the current and four
+ * previous points): the value at t1 of the polynomial of degree m in t that
+ * interpolates (T[j], X[j]), j = 0..m, written in Lagrange form.  The weights
+ * are formed in FP64, w_j = prod_{i != j} (t1 - T_i) / (T_j - T_i) with the
+ * factors taken in increasing i, and the sum over j in increasing j is
+ * formed in L limbs.  X is [m+1][n] (X[0] the current point).
+ */
+static void lagrange_weights(int m, const double *T, double t1, double *w)
+{
+    for (int j = 0; j <= m; ++j) {
+        double wj = 1.0;
+        for (int i = 0; i <= m; ++i) {
+            if (i == j) continue;
+            double num = t1 - T[i];
+            double den = T[j] - T[i];
+            wj = wj * (num / den);
+        }
+        w[j] = wj;
+    }
+}
+
+static void extrapolate(int L, int m, int n, const double *T, cx *const *X, double t1, cx *out)
+{
+    double w[8];
+    lagrange_weights(m, T, t1, w);
+    for (int k = 0; k < n; ++k) {
+        cx acc = cx_scale(L, X[0][k], mp_d(w[0]));
+        for (int j = 1; j <= m; ++j) acc = cx_add(L, acc, cx_scale(L, X[j][k], mp_d(w[j])));
+        out[k] = acc;
+    }
+}
+
+/* Exported for the pins: out = p(t1) for the interpolant of (T[j], X[j]),
+ * X as [m+1][n][2][L]. */
+void ora_extrapolate(int L, int m, int n, const double *T, const double *X, double t1, double *out)
+{
+    cx *buf = (cx *)malloc(sizeof(cx) * (size_t)(m + 1) * n);
+    cx *rows[8];
+    for (int j = 0; j <= m; ++j) {
+        rows[j] = buf + (size_t)j * n;
+        for (int k = 0; k < n; ++k) rows[j][k] = load_cx(X + ((size_t)j * n + k) * 2 * L, L);
+    }
+    cx *o = (cx *)malloc(sizeof(cx) * n);
+    extrapolate(L, m, n, T, rows, t1, o);
+    for (int k = 0; k < n; ++k) store_cx(out + (size_t)k * 2 * L, L, o[k]);
+    free(o);
+    free(buf);
+}
+
+/*
  * Track one path from x (start solution, t = 0) to t = 1.  Step control:
- * h <- min(h, 1 - t); predict (secant from the last two accepted points, or
- * the current point on the first step); correct with at most max_newton
+ * h <- min(h, 1 - t); predict (with predictor_order 1 the secant through
+ * the last two accepted points; with order m >= 2 the extrapolation above
+ * through the current point and up to m previous accepted points, the secant
+ * while only one previous point exists; the current point on the first
+ * step); correct with at most max_newton
  * Newton steps, converged when ||dx|| <= tol_dx max(1, ||x||), failed when a
  * later step does not shrink the update or MGS is singular.  Accepted steps
  * advance t and count toward expansion of h (x expand after expand_after
@@ -766,6 +820,13 @@ int ora_track_path(int L, const ora_opts *o, int n_eq, int n_var, const int32_t 
     sys_degrees(&f, deg);
     cx gam = cx_d(gamma[0], gamma[1]);
     cx *x = (cx *)malloc(sizeof(cx) * n), *xp = (cx *)malloc(sizeof(cx) * n);
+    /* older accepted points for predictor orders 2..4: xq[0] is the one
+     * before xp, xq[2] the oldest */
+    cx *xq[3];
+    double tq[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < 3; ++q) xq[q] = (cx *)malloc(sizeof(cx) * n);
+    const int order = o->predictor_order < 1 ? 1 : (o->predictor_order > 4 ? 4 : o->predictor_order);
+    int nh = 0; /* accepted points before the current one that are kept */
     cx *xh = (cx *)malloc(sizeof(cx) * n), *dx = (cx *)malloc(sizeof(cx) * n);
     cx *hv = (cx *)malloc(sizeof(cx) * m), *jm = (cx *)malloc(sizeof(cx) * m * n);
     cx *w = (cx *)malloc(sizeof(cx) * m * (n + 1));
@@ -785,7 +846,12 @@ int ora_track_path(int L, const ora_opts *o, int n_eq, int n_var, const int32_t 
         double t1 = t + h;
         if (t1 >= 1.0 - 1e-15) t1 = 1.0;
         /* predict */
-        if (have_prev) {
+        const int mo = nh < order ? nh : order;
+        if (mo >= 2) {
+            double T[5] = {t, tp, tq[0], tq[1], tq[2]};
+            cx *X[5] = {x, xp, xq[0], xq[1], xq[2]};
+            extrapolate(L, mo, n, T, X, t1, xh);
+        } else if (have_prev) {
             double r = (t1 - t) / (t - tp);
             mp rr = mp_d(r);
             for (int j = 0; j < n; ++j) xh[j] = cx_add(L, x[j], cx_scale(L, cx_sub(L, x[j], xp[j]), rr));
@@ -810,9 +876,20 @@ int ora_track_path(int L, const ora_opts *o, int n_eq, int n_var, const int32_t 
             dprev = dn;
         }
         if (conv) {
+            if (order >= 2) {
+                cx *oldest = xq[2];
+                xq[2] = xq[1];
+                xq[1] = xq[0];
+                xq[0] = oldest;
+                for (int j = 0; j < n; ++j) xq[0][j] = xp[j];
+                tq[2] = tq[1];
+                tq[1] = tq[0];
+                tq[0] = tp;
+            }
             tp = t;
             for (int j = 0; j < n; ++j) xp[j] = x[j];
             have_prev = 1;
+            if (nh < 4) nh++;
             t = t1;
             for (int j = 0; j < n; ++j) x[j] = xh[j];
             if (++succ >= o->expand_after) {
@@ -857,5 +934,6 @@ int ora_track_path(int L, const ora_opts *o, int n_eq, int n_var, const int32_t 
     if (newton_out) *newton_out = newton;
     if (t_out) *t_out = t;
     free(deg); free(x); free(xp); free(xh); free(dx); free(hv); free(jm); free(w);
+    for (int q = 0; q < 3; ++q) free(xq[q]);
     return reason == R_SUCCESS ? 1 : -1;
 }

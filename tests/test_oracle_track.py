@@ -80,8 +80,9 @@ def _branch_endpoint(gamma, c, d, x0, steps=20000):
     return np.abs(w[-1]) ** (1.0 / d) * np.exp(1j * (theta0 + (ang[-1] - ang[0]) / d))
 
 
+@pytest.mark.parametrize("order", [1, 4])
 @pytest.mark.parametrize("L", [1, 2])
-def test_decoupled_closed_form(L):
+def test_decoupled_closed_form(L, order):
     rng = np.random.default_rng(7)
     n = 3
     deg = np.array([3, 2, 3], dtype=np.int32)
@@ -89,7 +90,7 @@ def test_decoupled_closed_form(L):
     s = synth.system_from_terms(n, [[(1, {i: int(deg[i])}), (-cs[i], {})] for i in range(n)])
     gamma = synth.unit_complex(rng)
     B = int(np.prod(deg))
-    r = oracle.track(s, gamma, range(B), oracle.Opts(prec=L))
+    r = oracle.track(s, gamma, range(B), oracle.Opts(prec=L, predictor_order=order))
     assert np.all(r["status"] == 1)
     for p in range(B):
         x0 = _cx(oracle.start_solution(1, deg, p))
@@ -121,10 +122,11 @@ def _residual_ok(s, r, L, c=256.0):
     return np.all(res <= c * U[L] * np.maximum(sv, 1.0))
 
 
+@pytest.mark.parametrize("order", [1, 4])
 @pytest.mark.parametrize("L", [1, 2])
-def test_bezout_count_small(L):
+def test_bezout_count_small(L, order):
     s = synth.tracking_small()
-    r = oracle.track(s, synth.gamma_of(s), range(8), oracle.Opts(prec=L))
+    r = oracle.track(s, synth.gamma_of(s), range(8), oracle.Opts(prec=L, predictor_order=order))
     assert np.all(r["status"] == 1)
     E = _cx(r["x"])
     for a in range(8):
@@ -133,12 +135,13 @@ def test_bezout_count_small(L):
     assert _residual_ok(s, r, L)
 
 
-def test_bezout_count_cubic_n3():
+@pytest.mark.parametrize("order", [1, 4])
+def test_bezout_count_cubic_n3(order):
     """n = 3, degree 3 per equation (x_i^3, 1, 6 random others): 27 distinct endpoints."""
     rng = np.random.default_rng(12)
     eqs = [synth._equation_with_anchor(rng, [0, 1, 2], i, 3, 8) for i in range(3)]
     s = synth.system_from_terms(3, eqs)
-    r = oracle.track(s, synth.unit_complex(rng), range(27), oracle.Opts(prec=1))
+    r = oracle.track(s, synth.unit_complex(rng), range(27), oracle.Opts(prec=1, predictor_order=order))
     assert np.all(r["status"] == 1)
     E = _cx(r["x"])
     d = np.abs(E[:, None, :] - E[None, :, :]).max(-1) + np.eye(27)
@@ -185,3 +188,47 @@ def test_forced_failures():
     f = synth.system_from_terms(2, [[(1, {0: 2}), (-1, {})], [(1, {1: 2}), (-1, {})]])
     r = oracle.track_path(f, g, np.zeros((2, 2, 1)), oracle.Opts())
     assert oracle.REASONS[r["reason"]] == "SINGULAR" and r["status"] == -1
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+@pytest.mark.parametrize("m", [2, 3, 4])
+def test_extrapolation_exact_on_polynomials(L, m):
+    """The predictor of order m reproduces every polynomial path of degree m
+    (up to the FP64 weights) and misses one of degree m + 1: checks the
+    nodes, the weights and the sum, including the node count."""
+    rng = np.random.default_rng(100 + 10 * m + L)
+    n = 3
+    # dyadic nodes (previous points at decreasing t) and coefficients, so
+    # every sample value is exact in double
+    T = np.array([0.5 - 0.0625 * j for j in range(m + 1)])
+    t1 = 0.5 + 0.125
+    for deg, exact in ((m, True), (m + 1, False)):
+        cre = rng.integers(-8, 9, size=(n, deg + 1)) / 8.0
+        cim = rng.integers(-8, 9, size=(n, deg + 1)) / 8.0
+        cre[:, deg] += np.where(cre[:, deg] == 0, 1.0, 0.0)   # keep the top degree
+        P = lambda tt: (np.polyval(cre[:, ::-1].T, tt) + 1j * np.polyval(cim[:, ::-1].T, tt))
+        X = np.zeros((m + 1, n, 2, L))
+        for j in range(m + 1):
+            z = P(T[j])
+            X[j, :, 0, 0], X[j, :, 1, 0] = z.real, z.imag
+        got = oracle.extrapolate(L, T, X, t1)
+        ref = P(t1)
+        err = np.abs((got[:, 0, :].sum(-1) + 1j * got[:, 1, :].sum(-1)) - ref).max()
+        scale = max(1.0, np.abs(ref).max())
+        if exact:
+            assert err <= 1e-13 * scale, (deg, err)
+        else:
+            assert err > 1e-6, (deg, err)
+
+
+def test_extrapolation_order_one_is_the_secant():
+    """With two nodes the Lagrange form is the secant x + r (x - xp)."""
+    L = 2
+    T = np.array([0.4, 0.3])
+    X = np.zeros((2, 1, 2, L))
+    X[0, 0, 0, 0], X[0, 0, 1, 0] = 1.25, -0.5
+    X[1, 0, 0, 0], X[1, 0, 1, 0] = 0.75, 0.25
+    got = oracle.extrapolate(L, T, X, 0.55)
+    r = (0.55 - 0.4) / (0.4 - 0.3)
+    ref = complex(1.25, -0.5) + r * (complex(1.25, -0.5) - complex(0.75, 0.25))
+    assert abs(complex(got[0, 0].sum(), got[0, 1].sum()) - ref) <= 1e-15
