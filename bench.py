@@ -129,12 +129,12 @@ def time_eval(ph, torch, S, sysm, L, npts, steps, warmup, gamma, rng=None):
     return ms, ok, x, t
 
 
-def time_track(ph, torch, sysm, L, mixed, npaths, reps=1):
+def time_track(ph, torch, sysm, L, mixed, npaths, reps=1, order=1):
     """paths/s of ph_track on the first npaths start solutions (roots of unity)."""
     from paper_1505_00383_amd import synth
     S = ph.System(sysm)
     g = synth.gamma_of(sysm)
-    opts = ph.track_opts(prec=L, mixed=mixed)
+    opts = ph.track_opts(prec=L, mixed=mixed, predictor_order=order)
     ph.track(S, g, min(npaths, 64), opts)          # warm-up (module load, caches)
     st = torch.cuda.current_stream()
     best = None
@@ -312,6 +312,14 @@ def tracking_extras(ph, torch):
         "qd_endpoint_agreement_1e-48": endpoint_agreement(ph, q_m, q_p, 16, 4, sub, 1e-48)}
     full, _ = time_track(ph, torch, q16, 4, 1, 2 ** 16)
     out["track_n16_d2_qd_mixed_65536paths"] = full
+    # the fourth-order predictor (current and four previous points)
+    c4, _ = time_track(ph, torch, cub, 2, 1, B, reps=2, order=4)
+    f4, _ = time_track(ph, torch, q16, 4, 1, 2 ** 16, order=4)
+    out["predictor_order4"] = {
+        "track_n8_d3_6561paths_dd_mixed": c4,
+        "over_secant_n8_d3": c4["paths_per_s"] / dd_m["paths_per_s"],
+        "track_n16_d2_65536paths_qd_mixed": f4,
+        "over_secant_n16_d2": f4["paths_per_s"] / full["paths_per_s"]}
     return out
 
 

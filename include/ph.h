@@ -159,7 +159,11 @@ int ph_eval_autotune(ph_system *target, const ph_system *start, const double gam
  *   mixed           1: Newton update solved in complex FP64 from the rounded
  *                   Jacobian and residual, added to the prec-limb point
  *                   (refinement); 0: every step in prec limbs
- *   predictor_order 1 (secant; zero order on the first step)
+ *   predictor_order 1: secant (zero order on the first step); 2..4:
+ *                   extrapolation through the current and up to that many
+ *                   previous accepted points, per coordinate (Section 2's
+ *                   fourth-order predictor at 4); the secant while only one
+ *                   previous point exists
  *   max_newton      corrector steps per predictor step (3)
  *   expand_after    successes before the step grows (3)
  *   polish_max      Newton steps of the polish at t = 1 (8)
@@ -200,7 +204,7 @@ int ph_track_opts_default(ph_track_opts *o);
 /*
  * ph_track -- track npaths solution paths of gamma (1-t) g + t f = 0 from t = 0
  * to t = 1 (Section 2, Tables 1-3): per path its own t and step size,
- * predict (secant; zero order on the first step), evaluate-correct with
+ * predict (secant or extrapolation of order 2..4), evaluate-correct with
  * Newton steps solved by MGS least squares until converged (at most
  * max_newton per step), step-size control, status 1 / -1, and a Newton polish
  * at t = 1.  Paths run in a persistent kernel that refills lanes from a
@@ -220,7 +224,7 @@ int ph_track_opts_default(ph_track_opts *o);
  *   rep     : host report (nullable)
  * Synchronous: returns after the stream has finished (it fills rep).
  * Allocates a few KB of device scratch per call.  Errors: PH_EINVAL,
- * PH_EUNSUPPORTED (non-square, n > 32, k > 8, predictor_order != 1, degrees
+ * PH_EUNSUPPORTED (non-square, n > 32, k > 8, predictor_order outside 1..4, degrees
  * without closed-form roots of unity), PH_ENOMEM, PH_EHIP.
  */
 int ph_track(const ph_system *target, const ph_system *start, const double gamma[2],

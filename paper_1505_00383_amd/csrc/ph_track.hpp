@@ -51,6 +51,8 @@ struct TrackArgs {
     unsigned long long *stats;  // [0] steps [1] rejected [2] newton iterations [3 + reason] counts
     unsigned int *active;       // round schedule: waves still active after a launch
     void *state;                // round schedule: per-lane slot state
+    double *hist;               // predictor orders 2..4: three older points per lane slot,
+    int64_t hist_ld;            //   rows [q][re,im][limb], hist_ld = lane slots of the launch
     int rounds;                 // round schedule: rounds per launch
     ph_track_opts o;
     double polish_tol;

@@ -149,12 +149,16 @@ enum : int { PH_EMPTY = 0, PH_STEP = 1, PH_CORRECT = 2, PH_POLISH = 3, PH_RETIRE
 
 // Everything a lane carries from one round to the next.  The path-level
 // fields are identical in all lanes of a group; x, xp, xh are coordinate i.
+// nh counts the accepted points before the current one that the predictor
+// may use (x_p and, for orders above one, up to three older ones whose
+// coordinates live in the history buffer and whose t values are tq).
 template <int L>
 struct Slot {
-    int phase, sidx, n, succ, it, have_prev, pit;
+    int phase, sidx, n, succ, it, have_prev, pit, nh;
     int32_t steps, rejected, newton;
     int64_t gid;
     double t, tp, t1, h, dprev;
+    double tq[3];
     C<L> x, xp, xh;
 };
 
@@ -162,11 +166,29 @@ template <int L>
 __device__ __forceinline__ void slot_init(Slot<L> &s)
 {
     s.phase = PH_EMPTY;
-    s.sidx = s.n = s.succ = s.it = s.have_prev = s.pit = 0;
+    s.sidx = s.n = s.succ = s.it = s.have_prev = s.pit = s.nh = 0;
     s.steps = s.rejected = s.newton = 0;
     s.gid = 0;
     s.t = s.tp = s.t1 = s.h = s.dprev = 0.0;
+    s.tq[0] = s.tq[1] = s.tq[2] = 0.0;
     s.x = s.xp = s.xh = c_zero<L>();
+}
+
+// Weights of the extrapolation predictor of order m (Section 2): the
+// Lagrange basis of the nodes T[0..m] evaluated at t1, each a product of
+// FP64 factors (t1 - T_i) / (T_j - T_i) in increasing i.
+__device__ __forceinline__ void lagrange_weights(int m, const double *T, double t1, double *w)
+{
+    for (int j = 0; j <= m; ++j) {
+        double wj = 1.0;
+        for (int i = 0; i <= m; ++i) {
+            if (i == j) continue;
+            const double num = t1 - T[i];
+            const double den = T[j] - T[i];
+            wj = wj * (num / den);
+        }
+        w[j] = wj;
+    }
 }
 
 // Run at most max_rounds rounds of the tracker on the slots of this wave, or
@@ -191,7 +213,28 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
     };
 
     int phase = S.phase, sidx = S.sidx, n = S.n, succ = S.succ, it = S.it;
-    int have_prev = S.have_prev, pit = S.pit;
+    int have_prev = S.have_prev, pit = S.pit, nh = S.nh;
+    double tq0 = S.tq[0], tq1 = S.tq[1], tq2 = S.tq[2];
+    const int order = o.predictor_order;
+    // older history points of this lane's coordinate: [q][re,im][limb] rows
+    // of the history buffer, one column per lane slot
+    const int64_t hcol = (int64_t)blockIdx.x * 64 + lane;
+    auto hist_get = [&](int q) -> C<L> {
+        C<L> z;
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            z.re.v[l] = a.hist[((int64_t)(q * 2 + 0) * L + l) * a.hist_ld + hcol];
+            z.im.v[l] = a.hist[((int64_t)(q * 2 + 1) * L + l) * a.hist_ld + hcol];
+        }
+        return z;
+    };
+    auto hist_put = [&](int q, const C<L> &z) {
+#pragma unroll
+        for (int l = 0; l < L; ++l) {
+            a.hist[((int64_t)(q * 2 + 0) * L + l) * a.hist_ld + hcol] = z.re.v[l];
+            a.hist[((int64_t)(q * 2 + 1) * L + l) * a.hist_ld + hcol] = z.im.v[l];
+        }
+    };
     int32_t steps = S.steps, rejected = S.rejected, newton = S.newton;
     int64_t gid = S.gid;
     double t = S.t, tp = S.tp, t1 = S.t1, h = S.h, dprev = S.dprev;
@@ -255,7 +298,7 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
                 xh = x;
                 t = tp = 0.0;
                 h = o.h_init;
-                succ = it = have_prev = pit = 0;
+                succ = it = have_prev = pit = nh = 0;
                 steps = rejected = newton = 0;
                 phase = PH_STEP;
             }
@@ -280,7 +323,16 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
                 if (h > 1.0 - t) h = 1.0 - t;
                 t1 = t + h;
                 if (t1 >= 1.0 - 1e-15) t1 = 1.0;
-                if (have_prev) {
+                const int mo = nh < order ? nh : order;
+                if (mo >= 2) {
+                    // the current point and mo previous accepted points
+                    const double T[5] = {t, tp, tq0, tq1, tq2};
+                    double w[5];
+                    lagrange_weights(mo, T, t1, w);
+                    C<L> acc = c_add<L>(c_mul_d<L>(x, w[0]), c_mul_d<L>(xp, w[1]));
+                    for (int j = 2; j <= mo; ++j) acc = c_add<L>(acc, c_mul_d<L>(hist_get(j - 2), w[j]));
+                    xh = acc;
+                } else if (have_prev) {
                     const double r = (t1 - t) / (t - tp);
                     xh = c_add<L>(x, c_mul_d<L>(c_sub<L>(x, xp), r));
                 } else {
@@ -436,9 +488,19 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
                 }
             }
             if (accept) {
+                if (order >= 2) {
+                    // shift the history: older points move down, x_p joins
+                    if (nh >= 3) hist_put(2, hist_get(1));
+                    if (nh >= 2) hist_put(1, hist_get(0));
+                    hist_put(0, xp);
+                    tq2 = tq1;
+                    tq1 = tq0;
+                    tq0 = tp;
+                }
                 tp = t;
                 xp = x;
                 have_prev = 1;
+                if (nh < 4) ++nh;
                 t = t1;
                 x = xh;
                 if (++succ >= o.expand_after) {
@@ -495,6 +557,10 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
     S.it = it;
     S.have_prev = have_prev;
     S.pit = pit;
+    S.nh = nh;
+    S.tq[0] = tq0;
+    S.tq[1] = tq1;
+    S.tq[2] = tq2;
     S.steps = steps;
     S.rejected = rejected;
     S.newton = newton;

@@ -84,8 +84,8 @@ namespace ph {
 static int check_opts(const ph_track_opts &o)
 {
     if (o.prec != 1 && o.prec != 2 && o.prec != 4) return fail(PH_EINVAL, "opts.prec must be 1, 2 or 4");
-    if (o.predictor_order != 1)
-        return fail(PH_EUNSUPPORTED, "only the secant predictor (order 1) is implemented");
+    if (o.predictor_order < 1 || o.predictor_order > 4)
+        return fail(PH_EUNSUPPORTED, "predictor_order must be 1 (secant) to 4");
     if (o.max_newton < 1 || o.expand_after < 1 || o.polish_max < 0 || o.max_steps < 0)
         return fail(PH_EINVAL, "invalid iteration counts in opts");
     if (!(o.h_init > 0) || !(o.h_max > 0) || !(o.h_min >= 0) || !(o.shrink > 0 && o.shrink < 1) ||
@@ -212,7 +212,7 @@ static int track_impl(int nsys, const ph_system *const *targets, const ph_system
     if (kmax > 8) return fail(PH_EUNSUPPORTED, "tracking supports terms with at most 8 factors");
 
     // ---- device buffers: descriptors, path ids, counters, slot state
-    DevBuf bdesc, bids, bctr, bstate;
+    DevBuf bdesc, bids, bctr, bstate, bhist;
     if (path_ids) {
         PH_HIP(hipMalloc(&bids.p, sizeof(int64_t) * total));
         PH_HIP(hipMemcpyAsync(bids.p, path_ids, sizeof(int64_t) * total, hipMemcpyHostToDevice, st));
@@ -265,6 +265,12 @@ static int track_impl(int nsys, const ph_system *const *targets, const ph_system
         a.cls[c].block_end = blocks;
     }
     const size_t lds = track_lds_bytes(prec, opts->mixed, np_max);
+    if (opts->predictor_order > 1) {
+        // three older points per lane slot, kept across launches
+        a.hist_ld = (int64_t)blocks * 64;
+        PH_HIP(hipMalloc(&bhist.p, sizeof(double) * 3 * 2 * prec * (size_t)a.hist_ld));
+        a.hist = static_cast<double *>(bhist.p);
+    }
 
     if (opts->schedule == PH_SCHED_GRAPH) {
         // round-based: slot state in global memory, {clear, round kernel}

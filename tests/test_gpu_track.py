@@ -37,18 +37,20 @@ def _rel(a, b):
     return d / np.maximum(1.0, nb)
 
 
-def _parity(sysm, gamma, L, res, paths, oracle_mixed=0, note=""):
+def _parity(sysm, gamma, L, res, paths, oracle_mixed=0, note="", order=1):
     """Compare GPU endpoints with the oracle's plain track; arbitrate jumps."""
     npaths = len(paths)
     xg = _x_end(res, sysm.n_var, L, npaths)
-    ref = oracle.track(sysm, gamma, paths, oracle.Opts(prec=L, mixed=oracle_mixed), threads=THREADS)
+    ref = oracle.track(sysm, gamma, paths, oracle.Opts(prec=L, mixed=oracle_mixed, predictor_order=order),
+                       threads=THREADS)
     both_ok = (res["status"] == 1) & (ref["status"] == 1)
     rel = _rel(xg, ref["x"])
     bad = np.where(both_ok & (rel > 1e-8))[0]
     jumps = 0
     for b in bad:
         fine = oracle.track(sysm, gamma, [paths[b]],
-                            oracle.Opts(prec=L, mixed=oracle_mixed, h_max=0.01, h_init=0.001))
+                            oracle.Opts(prec=L, mixed=oracle_mixed, h_max=0.01, h_init=0.001,
+                                        predictor_order=order))
         r2 = _rel(xg[b:b + 1], fine["x"])[0]
         assert fine["status"][0] == 1 and r2 <= 1e-8, (note, int(paths[b]), rel[b], r2)
         jumps += 1
@@ -300,3 +302,54 @@ def test_batch_full_workload_graph_schedule():
         if ref["status"][0] == 1 and res["status"][gi] == 1:
             r = _rel(X[gi:gi + 1, :s.n_var], ref["x"])[0]
             assert r <= 1e-8, (int(k), j, r)
+
+
+@pytest.mark.parametrize("L,mixed", [(1, 0), (2, 0), (2, 1), (4, 1)])
+def test_track_small_system_order4(L, mixed):
+    """Fourth-order predictor (current and four previous points): endpoints
+    against the oracle's order-4 track; in double the same decisions give the
+    same step counts."""
+    s = synth.tracking_small()
+    g = synth.gamma_of(s)
+    S = ph.System(s)
+    res = ph.track(S, g, 8, ph.track_opts(prec=L, mixed=mixed, predictor_order=4))
+    assert np.all(res["status"] == 1)
+    ref, rel = _parity(s, g, L, res, np.arange(8), note=f"n3 order4 mixed={mixed}", order=4)
+    assert np.all(rel <= 1e-8)
+    if L == 1:
+        assert np.mean(np.abs(res["steps"] - ref["steps"])) <= 0.1 * np.mean(ref["steps"])
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+def test_track_cubic_subset_higher_order(order):
+    s = synth.tracking_cubic()
+    g = synth.gamma_of(s)
+    S = ph.System(s)
+    paths = np.arange(40) * 157 % 6561
+    import torch
+    x0 = ph.start_solutions(S, 2, 0, 6561)[:, torch.as_tensor(paths, device="cuda")].contiguous()
+    res = ph.track(S, g, len(paths), ph.track_opts(prec=2, mixed=1, predictor_order=order), x_start=x0)
+    _parity(s, g, 2, res, paths, note=f"n8 d3 DD mixed order {order}", order=order)
+
+
+def test_track_quadratic16_subset_order4_qd_mixed():
+    s = synth.tracking_quadratic16()
+    g = synth.gamma_of(s)
+    S = ph.System(s)
+    res = ph.track(S, g, 16, ph.track_opts(prec=4, mixed=1, predictor_order=4))
+    _parity(s, g, 4, res, np.arange(16), note="n16 d2 QD mixed order 4", order=4)
+
+
+def test_order4_graph_schedule_matches_persistent_bitwise():
+    """The predictor history lives in device memory per lane slot: replaying
+    the round kernel from a graph gives bitwise the persistent results."""
+    s = synth.tracking_cubic()
+    g = synth.gamma_of(s)
+    S = ph.System(s)
+    a = ph.track(S, g, 300, ph.track_opts(prec=2, mixed=1, predictor_order=4))
+    b = ph.track(S, g, 300, ph.track_opts(prec=2, mixed=1, predictor_order=4, schedule=ph.SCHED_GRAPH,
+                                          rounds_per_launch=3, launches_per_sync=5))
+    import torch
+    assert (a["status"] == b["status"]).all() and (a["steps"] == b["steps"]).all()
+    assert torch.equal(a["x_end"], b["x_end"])
+    print(f"[gpu] order 4: steps/path {a['steps'].mean():.1f}", flush=True)
