@@ -44,10 +44,10 @@ PREC_NAME = {1: "complex double", 2: "complex double double", 4: "complex quad d
 # kernel sources they were taken with: any change to them reports null.
 TRAFFIC = {
     "eval_d_pinned_kernel": {
-        "bytes": 51217289 + 1107296256,   # read + write
-        "sources": {"paper_1505_00383_amd/csrc/eval.hip": "ae08e22d85b8d8a7",
+        "bytes": 52140016 + 1107296256,   # read + write
+        "sources": {"paper_1505_00383_amd/csrc/eval.hip": "c06af5bc83397961",
                     "paper_1505_00383_amd/csrc/ph_arith.hpp": "f4b035f2f8fac960",
-                    "paper_1505_00383_amd/csrc/system.cpp": "b5fa172bd9ad37e7"},
+                    "paper_1505_00383_amd/csrc/system.cpp": "a39441e3bdda09e4"},
     },
 }
 
@@ -356,6 +356,9 @@ def main():
     ap.add_argument("--prec", type=int, default=1, choices=[1, 2, 4])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--kernel", type=int, default=0,
+                    help="evaluation kernel choice of ph_eval_set_config for the timed launches "
+                         "(0 automatic; 5 the unfused three-kernel design)")
     ap.add_argument("--mode", default="eval", choices=["eval", "track_n16_qd", "track_batch", "copy"],
                     help="eval: the benchmark line; the others run one workload for profiling: "
                          "the 65536-path QD-mixed tracking, the 64-system batch, or a device "
@@ -382,12 +385,19 @@ def main():
     gamma = synth.gamma_of(sysm)
     npts = 65536
     S = ph.System(sysm)
+    if args.kernel:
+        ph.eval_set_config(S, L, args.kernel)
     ms, ok, x, t = time_eval(ph, torch, S, sysm, L, npts, args.steps, args.warmup, gamma)
+    if args.kernel:
+        ph.eval_set_config(S, L)
     fpp = flops_per_point(sysm, L)
     bpp = bytes_per_point(sysm, L)
     secs = ms * 1e-3
     achieved = fpp * npts / secs
     kname = "eval_d_pinned_kernel" if L == 1 else f"eval_kernel<{L},8,true,true>"
+    if args.kernel:
+        kname = {1: f"eval_kernel<{L},8,true,true>", 2: "eval_d_regrow_kernel<8>", 3: kname,
+                 4: "eval_d_fast_kernel", 5: "coeff_kernel + mon_kernel + sum_kernel"}[args.kernel]
     traffic = traffic_of(kname)
     result = {
         "metric": "eval+Jacobian points/sec (paths/sec to t=1 in extras), per precision",
