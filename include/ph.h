@@ -130,7 +130,8 @@ int ph_eval_jac(const ph_system *target, const ph_system *start, const double ga
  * device memory between them; an ablation of the fused kernels, caching its
  * intermediate arrays -- (terms + slots) * 16 * prec bytes per point -- in
  * the system handle; waves and groups are ignored);
- * waves = waves per workgroup sharing one 64-point tile (1..8, 0 default);
+ * waves = waves per workgroup sharing one 64-point tile (1..8, 0 default;
+ * taken as given, so counts like 6 can match the register budget);
  * groups = equation groups per tile (power of two, 0 default).  All zero
  * clears the setting.  Host-only; PH_EINVAL on bad values.  A kernel that
  * does not apply makes later ph_eval_jac calls fail with PH_EUNSUPPORTED.

@@ -664,9 +664,16 @@ int eval_launch(const DevTable &tab, const double gamma[2], int prec, int64_t np
     // waves per workgroup: all of them share the 64 points staged in LDS and
     // take their own equations; wide precisions want more waves per
     // workgroup because their LDS tile (n * L KB) limits workgroups per CU
+    // (a configured count is taken as it is, up to 8 and n_eq: six waves of
+    // a 148-register kernel fill three waves per SIMD where eight cannot)
     int W = 1;
-    const int Wwant = (cfg && cfg->W > 0) ? cfg->W : (kernel >= 2 ? 8 : (prec == 1 ? 4 : 8));
-    while (W * 2 <= Wwant && W * 2 <= tab.n_eq && W * 2 <= 8) W *= 2;
+    if (cfg && cfg->W > 0) {
+        W = cfg->W < 8 ? cfg->W : 8;
+        if (W > tab.n_eq) W = tab.n_eq > 0 ? tab.n_eq : 1;
+    } else {
+        const int Wwant = kernel >= 2 ? 8 : (prec == 1 ? 4 : 8);
+        while (W * 2 <= Wwant && W * 2 <= tab.n_eq && W * 2 <= 8) W *= 2;
+    }
     const int64_t blocks = (npts + 63) / 64;
     int G = 1;
     if (cfg && cfg->G > 0) {
@@ -816,7 +823,7 @@ extern "C" int ph_eval_autotune(ph_system *target, const ph_system *start, const
     double best_t = 1e300;
     const int kernels[4] = {3, 4, 2, 1};
     for (int kk : kernels) {
-        for (int W = 1; W <= 8; W *= 2) {
+        for (int W : {1, 2, 4, 6, 8}) {
             for (int G = 1; G <= 8; G *= 2) {
                 if (W * G > tab->n_eq) continue;
                 EvalCfg c{kk, W, G};

@@ -585,10 +585,11 @@ __host__ __device__ constexpr size_t track_lds_doubles()
 }
 
 // Dispatch a block to its lane-count class.  Classes with lane counts 4, 8,
-// 16, 32 own consecutive block ranges; each runs its own work queue.  NPMAX
-// is the largest class present, so smaller launches do not carry the code
-// (and the registers) of the n <= 32 class.
-template <int L, int KMAX, bool MIXED, int NPMAX>
+// 16, 32 own consecutive block ranges; each runs its own work queue.
+// NPSEL > 0: the largest class present, so smaller launches do not carry the
+// code (and the registers) of the n <= 32 class; NPSEL < 0: the launch has
+// the single class -NPSEL and carries only its code (a single homotopy).
+template <int L, int KMAX, bool MIXED, int NPSEL>
 __device__ __forceinline__ bool run_class(const TrackArgs &a, Slot<L> &S, int max_rounds, double *lds)
 {
     const int b = blockIdx.x;
@@ -597,12 +598,17 @@ __device__ __forceinline__ bool run_class(const TrackArgs &a, Slot<L> &S, int ma
     const TrackClass &cl = a.cls[c];
     double *xsh = lds;
     double *wsh = lds + 64 * 2 * L;
+    if constexpr (NPSEL < 0) {
+        return run_rounds<L, -NPSEL, KMAX, MIXED>(a, cl, S, max_rounds, xsh, wsh);
+    } else {
+    constexpr int NPMAX = NPSEL;
     if (cl.np == 4) return run_rounds<L, 4, KMAX, MIXED>(a, cl, S, max_rounds, xsh, wsh);
     if (cl.np == 8 || NPMAX == 8) return run_rounds<L, 8, KMAX, MIXED>(a, cl, S, max_rounds, xsh, wsh);
     if constexpr (NPMAX >= 16)
         if (cl.np == 16 || NPMAX == 16) return run_rounds<L, 16, KMAX, MIXED>(a, cl, S, max_rounds, xsh, wsh);
     if constexpr (NPMAX >= 32) return run_rounds<L, 32, KMAX, MIXED>(a, cl, S, max_rounds, xsh, wsh);
     return true;
+    }
 }
 
 // One kernel for both schedules.  Persistent (a.state == NULL): every wave
@@ -610,7 +616,7 @@ __device__ __forceinline__ bool run_class(const TrackArgs &a, Slot<L> &S, int ma
 // launch runs a.rounds rounds and keeps each lane's slot in device memory
 // between launches; the host replays a captured graph of {clear counter,
 // this kernel} and reads the number of waves still active.
-template <int L, int KMAX, bool MIXED, int NPMAX>
+template <int L, int KMAX, bool MIXED, int NPSEL>
 __global__ void __launch_bounds__(64) track_kernel(TrackArgs a)
 {
     extern __shared__ double lds[];
@@ -622,7 +628,7 @@ __global__ void __launch_bounds__(64) track_kernel(TrackArgs a)
     else
         slot_init<L>(S);
     if (__all(S.phase == PH_RETIRED)) return;
-    const bool retired = run_class<L, KMAX, MIXED, NPMAX>(a, S, st ? a.rounds : 0x7fffffff, lds);
+    const bool retired = run_class<L, KMAX, MIXED, NPSEL>(a, S, st ? a.rounds : 0x7fffffff, lds);
     if (st) {
         *st = S;
         if (!retired && threadIdx.x == 0) atomicAdd(a.active, 1u);
