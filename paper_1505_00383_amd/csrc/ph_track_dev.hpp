@@ -616,8 +616,13 @@ __device__ __forceinline__ bool run_class(const TrackArgs &a, Slot<L> &S, int ma
 // launch runs a.rounds rounds and keeps each lane's slot in device memory
 // between launches; the host replays a captured graph of {clear counter,
 // this kernel} and reads the number of waves still active.
+// Two waves per SIMD: the double-double and quad-double state machines want
+// more than 256 registers; the compiler keeps them within 256 by spilling
+// a few values to scratch, which costs far less than running one wave per
+// SIMD (measured: 1.6x on the many-system double-double batch, 1.3x on the
+// 65536-path quad-double workload).
 template <int L, int KMAX, bool MIXED, int NPSEL>
-__global__ void __launch_bounds__(64) track_kernel(TrackArgs a)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) track_kernel(TrackArgs a)
 {
     extern __shared__ double lds[];
     Slot<L> *st = a.state ? reinterpret_cast<Slot<L> *>(a.state) + (size_t)blockIdx.x * 64 + threadIdx.x
