@@ -182,6 +182,9 @@ int ph_eval_autotune(ph_system *target, const ph_system *start, const double gam
  *   rounds_per_launch   graph schedule: tracker rounds per kernel launch (8)
  *   launches_per_sync   graph schedule: graph replays between reads of the count (8)
  *   blocks_per_cu   workgroups per CU (0: the library's default, 8)
+ *   lanes_per_path  lanes that share one path (0: the next power of two >= n;
+ *                   4, 8, 16 or 32 to give each path more lanes than it
+ *                   has unknowns, which spreads few paths over more waves)
  */
 #define PH_SCHED_PERSISTENT 0
 #define PH_SCHED_GRAPH 1
@@ -190,6 +193,7 @@ typedef struct {
     double h_init, h_min, h_max, shrink, expand, tol_dx, diverge_norm, polish_tol;
     int64_t max_steps;
     int32_t schedule, rounds_per_launch, launches_per_sync, blocks_per_cu;
+    int32_t lanes_per_path;
 } ph_track_opts;
 
 /* Counts filled by ph_track when a report pointer is given. */
@@ -258,7 +262,8 @@ int ph_track_batch(int32_t nsys, const ph_system *const *targets, const double *
  * ph_track_autotune -- choose the launch shape of ph_track_batch (and of
  * ph_track with a total-degree start) for this batch: tracks a sample of
  * about `sample` paths (each system's first ones, in proportion to its path
- * count) under each candidate (schedule, rounds_per_launch, blocks_per_cu)
+ * count) under each candidate (schedule, rounds_per_launch, blocks_per_cu,
+ * lanes_per_path)
  * and writes *opts with the fastest into *tuned (every other field copied).
  * With PH_AUTOTUNE_CACHE naming a file, a previous choice for the same
  * systems, path counts, prec and mixed is read from it instead of timing, and

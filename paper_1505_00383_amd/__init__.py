@@ -42,7 +42,7 @@ class TrackOpts(ctypes.Structure):
                 ("diverge_norm", ctypes.c_double), ("polish_tol", ctypes.c_double),
                 ("max_steps", ctypes.c_int64), ("schedule", ctypes.c_int32),
                 ("rounds_per_launch", ctypes.c_int32), ("launches_per_sync", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("lanes_per_path", ctypes.c_int32)]
 
 
 SCHED_PERSISTENT, SCHED_GRAPH = 0, 1
@@ -349,7 +349,7 @@ def track_batch(systems, gammas, path_lists, opts: TrackOpts | None = None, stre
 
 def track_autotune(systems, gammas, path_lists, opts: TrackOpts | None = None,
                    sample: int = 16384, stream=None):
-    """Launch shape (schedule, rounds_per_launch, blocks_per_cu) for this batch,
+    """Launch shape (schedule, rounds_per_launch, blocks_per_cu, lanes_per_path) for this batch,
     timed on a proportional sample of its paths (ph_track_autotune).
     Returns (tuned TrackOpts, seconds of the sample under it; 0 from the cache)."""
     _torch()

@@ -443,5 +443,6 @@ extern "C" int ph_track_opts_default(ph_track_opts *o)
     o->rounds_per_launch = 8;
     o->launches_per_sync = 8;
     o->blocks_per_cu = 0;
+    o->lanes_per_path = 0;
     return PH_OK;
 }

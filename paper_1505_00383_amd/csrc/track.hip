@@ -91,6 +91,9 @@ static int check_opts(const ph_track_opts &o)
     if (!(o.h_init > 0) || !(o.h_max > 0) || !(o.h_min >= 0) || !(o.shrink > 0 && o.shrink < 1) ||
         !(o.expand >= 1) || !(o.tol_dx > 0) || !(o.diverge_norm > 0))
         return fail(PH_EINVAL, "invalid step-control constants in opts");
+    if (o.lanes_per_path != 0 && o.lanes_per_path != 4 && o.lanes_per_path != 8 &&
+        o.lanes_per_path != 16 && o.lanes_per_path != 32)
+        return fail(PH_EINVAL, "lanes_per_path must be 0, 4, 8, 16 or 32");
     return PH_OK;
 }
 
@@ -163,7 +166,7 @@ static int track_impl(int nsys, const ph_system *const *targets, const ph_system
             if (t->h.n_eq != n) return fail(PH_EUNSUPPORTED, "tracking needs square systems");
             if (n > 32) return fail(PH_EUNSUPPORTED, "tracking is limited to n <= 32");
             int cls = 0;
-            while (class_np[cls] < n) ++cls;
+            while (class_np[cls] < n || class_np[cls] < opts->lanes_per_path) ++cls;
             if (cls != c) continue;
             const DevTable *tab = nullptr;
             rc = get_table(t, start, &tab);
@@ -425,15 +428,16 @@ extern "C" int ph_track_autotune(int32_t nsys, const ph_system *const *targets, 
         if (FILE *f = std::fopen(cache, "r")) {
             char tag[16];
             unsigned long long k = 0;
-            int sch = 0, rnd = 0, bpc = 0;
+            int sch = 0, rnd = 0, bpc = 0, lanes = 0;
             double sec = 0;
             bool found = false;
             ph_track_opts o = *opts;
-            while (std::fscanf(f, "%15s %llx %d %d %d %lf", tag, &k, &sch, &rnd, &bpc, &sec) == 6) {
+            while (std::fscanf(f, "%15s %llx %d %d %d %d %lf", tag, &k, &sch, &rnd, &bpc, &lanes, &sec) == 7) {
                 if (std::strcmp(tag, "track") == 0 && k == key) {
                     o.schedule = sch;
                     o.rounds_per_launch = rnd;
                     o.blocks_per_cu = bpc;
+                    o.lanes_per_path = lanes;
                     found = true;
                 }
             }
@@ -461,16 +465,20 @@ extern "C" int ph_track_autotune(int32_t nsys, const ph_system *const *targets, 
     PH_HIP(hipMalloc(&bx.p, sizeof(double) * (size_t)maxn * 2 * opts->prec * ns));
     PH_HIP(hipMalloc(&bst.p, (size_t)ns));
 
-    // candidates: residency-limited workgroups per CU, both schedules
+    // candidates: residency-limited workgroups per CU, both schedules, the
+    // natural lane count and twice it (more waves for few paths)
     int np_max = 4;
     while (np_max < maxn) np_max *= 2;
-    const size_t lds = track_lds_bytes(opts->prec, opts->mixed, np_max);
-    const int lds_cap = (int)std::max<size_t>(1, (160 * 1024) / lds);
-    struct Cand { int sch, rnd, bpc; };
+    struct Cand { int sch, rnd, bpc, lanes; };
     std::vector<Cand> cands;
-    for (int bpc : {2, 4, 8, 12, 16})
-        if (bpc <= lds_cap || bpc == 2) cands.push_back({PH_SCHED_PERSISTENT, opts->rounds_per_launch, bpc});
-    for (int rnd : {4, 16}) cands.push_back({PH_SCHED_GRAPH, rnd, std::min(8, lds_cap)});
+    for (int lanes : {0, 2 * np_max}) {
+        if (lanes > 32) continue;
+        const int lcap = (int)std::max<size_t>(
+            1, (160 * 1024) / track_lds_bytes(opts->prec, opts->mixed, lanes ? lanes : np_max));
+        for (int bpc : {2, 4, 8, 12, 16})
+            if (bpc <= lcap || bpc == 2) cands.push_back({PH_SCHED_PERSISTENT, opts->rounds_per_launch, bpc, lanes});
+        for (int rnd : {4, 16}) cands.push_back({PH_SCHED_GRAPH, rnd, std::min(8, lcap), lanes});
+    }
     double best = 1e300;
     ph_track_opts bo = *opts;
     for (const Cand &c : cands) {
@@ -478,6 +486,7 @@ extern "C" int ph_track_autotune(int32_t nsys, const ph_system *const *targets, 
         o.schedule = c.sch;
         o.rounds_per_launch = c.rnd;
         o.blocks_per_cu = c.bpc;
+        o.lanes_per_path = c.lanes;
         ph_track_report r;
         rc = track_impl(nsys, targets, nullptr, gammas, off.data(), ids.data(), nullptr, ns, &o,
                         (double *)bx.p, (int8_t *)bst.p, nullptr, nullptr, &r, st);
@@ -491,8 +500,8 @@ extern "C" int ph_track_autotune(int32_t nsys, const ph_system *const *targets, 
     if (best_seconds) *best_seconds = best;
     if (cache) {
         if (FILE *f = std::fopen(cache, "a")) {
-            std::fprintf(f, "track %llx %d %d %d %.6f\n", (unsigned long long)key, bo.schedule,
-                         bo.rounds_per_launch, bo.blocks_per_cu, best);
+            std::fprintf(f, "track %llx %d %d %d %d %.6f\n", (unsigned long long)key, bo.schedule,
+                         bo.rounds_per_launch, bo.blocks_per_cu, bo.lanes_per_path, best);
             std::fclose(f);
         }
     }

@@ -353,3 +353,18 @@ def test_order4_graph_schedule_matches_persistent_bitwise():
     assert (a["status"] == b["status"]).all() and (a["steps"] == b["steps"]).all()
     assert torch.equal(a["x_end"], b["x_end"])
     print(f"[gpu] order 4: steps/path {a['steps'].mean():.1f}", flush=True)
+
+
+@pytest.mark.parametrize("lanes", [16, 32])
+def test_more_lanes_per_path_same_results(lanes):
+    """Giving each path more lanes than unknowns (idle rows and columns in
+    the group) changes nothing in the arithmetic: endpoints, status and step
+    counts are bitwise those of the natural lane count."""
+    s = synth.tracking_cubic()
+    g = synth.gamma_of(s)
+    S = ph.System(s)
+    a = ph.track(S, g, 400, ph.track_opts(prec=2, mixed=1))
+    b = ph.track(S, g, 400, ph.track_opts(prec=2, mixed=1, lanes_per_path=lanes))
+    import torch
+    assert (a["status"] == b["status"]).all() and (a["steps"] == b["steps"]).all()
+    assert torch.equal(a["x_end"], b["x_end"])

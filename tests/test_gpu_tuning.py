@@ -157,6 +157,7 @@ def test_track_autotune_choice_is_valid_and_cached(tmp_path, monkeypatch):
     assert sec > 0
     assert tuned.schedule in (ph.SCHED_PERSISTENT, ph.SCHED_GRAPH)
     assert 1 <= tuned.blocks_per_cu <= 16 and tuned.rounds_per_launch >= 1
+    assert tuned.lanes_per_path in (0, 4, 8, 16, 32)
     assert (tuned.prec, tuned.mixed, tuned.h_max) == (2, 1, base.h_max)
     print(f"[gpu] tuned schedule={tuned.schedule} rounds={tuned.rounds_per_launch} "
           f"blocks_per_cu={tuned.blocks_per_cu} sample {sec:.3f} s", flush=True)
@@ -167,5 +168,5 @@ def test_track_autotune_choice_is_valid_and_cached(tmp_path, monkeypatch):
     assert torch.equal(a["x_end"], b["x_end"])
     again, sec2 = ph.track_autotune(systems, gammas, paths, base, sample=400)
     assert sec2 == 0.0
-    assert (again.schedule, again.rounds_per_launch, again.blocks_per_cu) == \
-        (tuned.schedule, tuned.rounds_per_launch, tuned.blocks_per_cu)
+    assert (again.schedule, again.rounds_per_launch, again.blocks_per_cu, again.lanes_per_path) == \
+        (tuned.schedule, tuned.rounds_per_launch, tuned.blocks_per_cu, tuned.lanes_per_path)
