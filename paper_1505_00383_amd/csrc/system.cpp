@@ -44,8 +44,18 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
     std::vector<double> coef;
     int kmax = 0;
     std::vector<char> touched(nv);
+    // terms of each equation in order of their number of factors (stable):
+    // the tracker evaluates one equation per lane, and equal term shapes at
+    // equal positions keep the lanes of a wave on the same path through the
+    // sweep; the evaluation kernels are indifferent to the order
+    std::vector<int> order;
     auto emit = [&](const HostSystem &s, int i, int sel) {
-        for (int t = s.eq_term_off[i]; t < s.eq_term_off[i + 1]; ++t) {
+        order.clear();
+        for (int t = s.eq_term_off[i]; t < s.eq_term_off[i + 1]; ++t) order.push_back(t);
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            return s.term_fac_off[x + 1] - s.term_fac_off[x] < s.term_fac_off[y + 1] - s.term_fac_off[y];
+        });
+        for (int t : order) {
             int a = s.term_fac_off[t], b = s.term_fac_off[t + 1];
             int4 d;
             d.x = b - a;
