@@ -11,36 +11,61 @@
 
 namespace ph {
 
-template <int NP>
+// Partner value for step O (1, 2, 4, 8, 16) of a group reduction.  The
+// first four steps stay inside a 16-lane row and use DPP moves (quad
+// permutations, then the half-row and row mirrors, which pair each lane
+// with one in the other half of its 8- or 16-lane block, as a reduction
+// needs); the step across rows uses a lane permute.  After every step all
+// lanes of a block hold bitwise the same value, because each pair adds the
+// same two operands.
+template <int O>
+__device__ __forceinline__ double red_partner(double v)
+{
+    if constexpr (O >= 16) {
+        return __shfl_xor(v, O);
+    } else {
+        constexpr int ctrl = O == 1 ? 0xB1 : (O == 2 ? 0x4E : (O == 4 ? 0x141 : 0x140));
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, ctrl, 0xF, 0xF, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), ctrl, 0xF, 0xF, false);
+        return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+    }
+}
+
+template <int NP, int O = 1>
 __device__ __forceinline__ double gsum_d(double v)
 {
-#pragma unroll
-    for (int o = 1; o < NP; o <<= 1) v += __shfl_xor(v, o);
-    return v;
+    if constexpr (O < NP) {
+        v += red_partner<O>(v);
+        return gsum_d<NP, 2 * O>(v);
+    } else {
+        return v;
+    }
 }
 
-template <int NP>
+template <int NP, int O = 1>
 __device__ __forceinline__ double gmax_d(double v)
 {
-#pragma unroll
-    for (int o = 1; o < NP; o <<= 1) {
-        double u = __shfl_xor(v, o);
+    if constexpr (O < NP) {
+        const double u = red_partner<O>(v);
         v = (v != v || u != u) ? (v + u) : fmax(v, u);  // NaN propagates
+        return gmax_d<NP, 2 * O>(v);
+    } else {
+        return v;
     }
-    return v;
 }
 
-template <int NP, int L>
+template <int NP, int L, int O = 1>
 __device__ __forceinline__ R<L> gsum_r(R<L> v)
 {
-#pragma unroll
-    for (int o = 1; o < NP; o <<= 1) {
+    if constexpr (O < NP) {
         R<L> u;
 #pragma unroll
-        for (int l = 0; l < L; ++l) u.v[l] = __shfl_xor(v.v[l], o);
-        v = r_add<L>(v, u);
+        for (int l = 0; l < L; ++l) u.v[l] = red_partner<O>(v.v[l]);
+        return gsum_r<NP, L, 2 * O>(r_add<L>(v, u));
+    } else {
+        return v;
     }
-    return v;
 }
 
 template <int NP, int L>
