@@ -179,7 +179,7 @@ int ph_eval_autotune(ph_system *target, const ph_system *start, const double gam
  *                   a hipGraph and replayed; slot state stays in device memory
  *                   and only the count of active waves crosses to the host,
  *                   Section 2, Table 3)
- *   rounds_per_launch   graph schedule: tracker rounds per kernel launch (8)
+ *   rounds_per_launch   graph schedule: tracker rounds per kernel launch (32)
  *   launches_per_sync   graph schedule: graph replays between reads of the count (8)
  *   blocks_per_cu   workgroups per CU (0: the library's default, 8)
  *   lanes_per_path  lanes that share one path (0: the next power of two >= n;

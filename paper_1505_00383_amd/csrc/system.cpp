@@ -450,7 +450,7 @@ extern "C" int ph_track_opts_default(ph_track_opts *o)
     o->polish_tol = -1.0;
     o->max_steps = 100000;
     o->schedule = PH_SCHED_PERSISTENT;
-    o->rounds_per_launch = 8;
+    o->rounds_per_launch = 32;
     o->launches_per_sync = 8;
     o->blocks_per_cu = 0;
     o->lanes_per_path = 0;

@@ -477,7 +477,7 @@ extern "C" int ph_track_autotune(int32_t nsys, const ph_system *const *targets, 
             1, (160 * 1024) / track_lds_bytes(opts->prec, opts->mixed, lanes ? lanes : np_max));
         for (int bpc : {2, 4, 8, 12, 16})
             if (bpc <= lcap || bpc == 2) cands.push_back({PH_SCHED_PERSISTENT, opts->rounds_per_launch, bpc, lanes});
-        for (int rnd : {4, 16}) cands.push_back({PH_SCHED_GRAPH, rnd, std::min(8, lcap), lanes});
+        for (int rnd : {8, 32, 128}) cands.push_back({PH_SCHED_GRAPH, rnd, std::min(8, lcap), lanes});
     }
     double best = 1e300;
     ph_track_opts bo = *opts;
