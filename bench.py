@@ -356,6 +356,8 @@ def main():
     ap.add_argument("--prec", type=int, default=1, choices=[1, 2, 4])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="time the library's default kernel choice instead of the autotuned one")
     ap.add_argument("--kernel", type=int, default=0,
                     help="evaluation kernel choice of ph_eval_set_config for the timed launches "
                          "(0 automatic; 5 the unfused three-kernel design)")
@@ -385,8 +387,14 @@ def main():
     gamma = synth.gamma_of(sysm)
     npts = 65536
     S = ph.System(sysm)
+    tuned_cfg = None
     if args.kernel:
         ph.eval_set_config(S, L, args.kernel)
+    elif not args.no_autotune:
+        # the library's autotuner picks kernel and tiling on this workload
+        x0, t0 = synth.torus_points(sysm, npts, L)
+        ph.eval_autotune(S, ph.to_soa(x0), npts, L, torch.as_tensor(t0, dtype=torch.float64).cuda(), gamma)
+        tuned_cfg = ph.eval_get_config(S, L)
     ms, ok, x, t = time_eval(ph, torch, S, sysm, L, npts, args.steps, args.warmup, gamma)
     if args.kernel:
         ph.eval_set_config(S, L)
@@ -395,9 +403,10 @@ def main():
     secs = ms * 1e-3
     achieved = fpp * npts / secs
     kname = "eval_d_pinned_kernel" if L == 1 else f"eval_kernel<{L},8,true,true>"
-    if args.kernel:
+    kchoice = args.kernel or (tuned_cfg[0] if tuned_cfg else 0)
+    if kchoice:
         kname = {1: f"eval_kernel<{L},8,true,true>", 2: "eval_d_regrow_kernel<8>", 3: kname,
-                 4: "eval_d_fast_kernel", 5: "coeff_kernel + mon_kernel + sum_kernel"}[args.kernel]
+                 4: "eval_d_fast_kernel", 5: "coeff_kernel + mon_kernel + sum_kernel"}[kchoice]
     traffic = traffic_of(kname)
     result = {
         "metric": "eval+Jacobian points/sec (paths/sec to t=1 in extras), per precision",
@@ -416,6 +425,9 @@ def main():
                                f"vars, exponents 1..3, 65536 torus points, {PREC_NAME[L]}",
                    "prec_limbs": L, "points": npts, "n": 32, "terms": int(sysm.n_terms),
                    "parallelism": "single GPU"},
+        "launch": ({"kernel": tuned_cfg[0], "waves_per_workgroup": tuned_cfg[1],
+                    "equation_groups": tuned_cfg[2], "chosen_by": "ph_eval_autotune"}
+                   if tuned_cfg else {"chosen_by": "--kernel" if args.kernel else "default"}),
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": traffic,
                      "traffic_unit": "bytes per launch", "kernel": kname,
@@ -429,11 +441,17 @@ def main():
         for L2 in (1, 2, 4):
             if L2 == L:
                 continue
+            cfg2 = None
+            if not args.no_autotune:
+                x0, t0 = synth.torus_points(sysm, npts, L2)
+                ph.eval_autotune(S, ph.to_soa(x0), npts, L2,
+                                 torch.as_tensor(t0, dtype=torch.float64).cuda(), gamma)
+                cfg2 = ph.eval_get_config(S, L2)
             ms2, ok2, _, _ = time_eval(ph, torch, S, sysm, L2, npts, max(3, args.steps // 4), 1, gamma)
             f2 = flops_per_point(sysm, L2)
             extras[f"eval_prec{L2}"] = {"points_per_s": npts / (ms2 * 1e-3), "ms": ms2,
                                         "fp64_frac": f2 * npts / (ms2 * 1e-3) / PEAK_FP64,
-                                        "finite": ok2}
+                                        "launch": cfg2, "finite": ok2}
         extras["eval_n16_d2_hbm_1M_points_double"] = hbm_extra(ph, torch, max(3, args.steps // 4))
         extras["unfused_three_kernel_ablation"] = unfused_extra(ph, torch, S, sysm, gamma, 5)
         extras.update(tracking_extras(ph, torch))

@@ -140,6 +140,14 @@ int ph_eval_set_config(ph_system *target, const ph_system *start, int32_t prec, 
                        int32_t waves, int32_t groups);
 
 /*
+ * ph_eval_get_config -- the configuration pinned or tuned for (target, start,
+ * prec) in this handle (all zero: automatic).  Host-only; PH_EINVAL on null
+ * pointers.
+ */
+int ph_eval_get_config(const ph_system *target, const ph_system *start, int32_t prec,
+                       int32_t *kernel, int32_t *waves, int32_t *groups);
+
+/*
  * ph_eval_autotune -- time every applicable (kernel, waves, groups) choice of
  * ph_eval_jac on the caller's buffers (same arguments as ph_eval_jac; the
  * outputs are overwritten with a valid result) and keep the fastest for

@@ -25,7 +25,7 @@ REASONS = {0: "NONE", 1: "SUCCESS", 2: "DIVERGED", 3: "STEP_UNDERFLOW", 4: "MAX_
 EXPORTED = ["ph_system_create", "ph_system_destroy", "ph_system_info", "ph_system_degrees",
             "ph_start_solutions", "ph_eval_jac", "ph_track_opts_default", "ph_last_error",
             "ph_arith_probe", "ph_track", "ph_track_batch", "ph_eval_set_config",
-            "ph_eval_autotune", "ph_track_autotune"]
+            "ph_eval_autotune", "ph_track_autotune", "ph_eval_get_config"]
 
 # ph_eval_set_config kernels
 EVAL_AUTO, EVAL_GENERAL, EVAL_REGROW, EVAL_FAST, EVAL_FAST_VECROW, EVAL_UNFUSED = 0, 1, 2, 3, 4, 5
@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH):
     L.ph_track.argtypes = [P, P, P, i64, P, i64, P, P, P, P, P, P, P]
     L.ph_track_batch.argtypes = [i32, P, P, P, P, P, P, i64, P, P, P, P, P]
     L.ph_eval_set_config.argtypes = [P, P, i32, i32, i32, i32]
+    L.ph_eval_get_config.argtypes = [P, P, i32, P, P, P]
     L.ph_eval_autotune.argtypes = [P, P, P, i32, i64, P, P, i64, P, P, P, P]
     L.ph_track_autotune.argtypes = [i32, P, P, P, P, P, i64, P, P, P]
     for name in EXPORTED:
@@ -230,6 +231,14 @@ def eval_set_config(sys: System, prec: int, kernel: int = EVAL_AUTO, waves: int 
     all zero restores the automatic choice."""
     _check(load_library().ph_eval_set_config(sys.handle, None if start is None else start.handle,
                                              prec, kernel, waves, groups))
+
+
+def eval_get_config(sys: System, prec: int, start: System | None = None):
+    """(kernel, waves, groups) pinned or tuned for (sys, start, prec); zeros: automatic."""
+    k, w, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().ph_eval_get_config(sys.handle, None if start is None else start.handle, prec,
+                                             ctypes.byref(k), ctypes.byref(w), ctypes.byref(g)))
+    return k.value, w.value, g.value
 
 
 def eval_autotune(sys: System, x_soa, npts: int, prec: int, t=None, gamma=1.0 + 0j,

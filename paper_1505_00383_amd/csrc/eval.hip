@@ -804,6 +804,19 @@ extern "C" int ph_eval_set_config(ph_system *target, const ph_system *start, int
     return PH_OK;
 }
 
+extern "C" int ph_eval_get_config(const ph_system *target, const ph_system *start, int32_t prec,
+                                  int32_t *kernel, int32_t *waves, int32_t *groups)
+{
+    if (!target || !kernel || !waves || !groups) return fail(PH_EINVAL, "null argument");
+    ph_system *tg = const_cast<ph_system *>(target);
+    std::lock_guard<std::mutex> lk(tg->mu);
+    auto it = tg->eval_cfg.find({start, prec});
+    *kernel = it == tg->eval_cfg.end() ? 0 : it->second.kernel;
+    *waves = it == tg->eval_cfg.end() ? 0 : it->second.W;
+    *groups = it == tg->eval_cfg.end() ? 0 : it->second.G;
+    return PH_OK;
+}
+
 extern "C" int ph_eval_autotune(ph_system *target, const ph_system *start, const double gamma[2],
                                 int32_t prec, int64_t npts, const double *t, const double *x,
                                 int64_t ld, double *val, double *jac, void *stream,
