@@ -254,7 +254,9 @@ int ph_track(const ph_system *target, const ph_system *start, const double gamma
  *   gammas   : host [nsys][2]
  *   path_off : host int64[nsys + 1], path_off[0] = 0
  *   path_ids : host int64[path_off[nsys]] multi-index numbers of the tracked
- *              start solutions of each system, or NULL (0 .. npaths_s - 1)
+ *              start solutions of each system, or NULL (0 .. npaths_s - 1);
+ *              PH_EINVAL for a number outside 0 .. Bezout number - 1 (or,
+ *              without path_ids, for more paths than start solutions)
  *   x_end, status, reason, steps : indexed by the global path index (ld >= total)
  * A path takes the next power of two >= its system's n lanes (4, 8, 16 or
  * 32); systems of one lane count share a work queue and a range of

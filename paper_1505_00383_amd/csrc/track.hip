@@ -202,6 +202,15 @@ static int track_impl(int nsys, const ph_system *const *targets, const ph_system
                     if (dg < 1 || 12 % dg != 0 || dg == 12)
                         return fail(PH_EUNSUPPORTED, "in-kernel start solutions need degrees in {1,2,3,4,6}");
                 }
+                // every path number names a start solution: 0 <= id < Bezout number
+                const int64_t bez = overflow ? INT64_MAX : r;
+                if (path_ids) {
+                    for (int64_t q2 = path_off[s]; q2 < path_off[s + 1]; ++q2)
+                        if (path_ids[q2] < 0 || path_ids[q2] >= bez)
+                            return fail(PH_EINVAL, "path id outside 0 .. Bezout number - 1");
+                } else if (d.npaths > bez) {
+                    return fail(PH_EINVAL, "more paths than start solutions");
+                }
             }
             kmax = std::max(kmax, tab->kmax);
             // work estimate: lanes times terms per equation

@@ -368,3 +368,27 @@ def test_more_lanes_per_path_same_results(lanes):
     import torch
     assert (a["status"] == b["status"]).all() and (a["steps"] == b["steps"]).all()
     assert torch.equal(a["x_end"], b["x_end"])
+
+
+def test_empty_inputs_and_empty_batch_member():
+    """No paths at all returns at once with an empty report; a batch member
+    with no paths between two others changes nothing for them."""
+    s = synth.tracking_small()
+    g = synth.gamma_of(s)
+    S = ph.System(s)
+    r0 = ph.track(S, g, 0, ph.track_opts(prec=2, mixed=1))
+    assert r0["report"]["n_success"] == 0 and r0["report"]["steps"] == 0
+    cub = synth.tracking_cubic()
+    C = ph.System(cub)
+    gc = synth.gamma_of(cub)
+    paths = [np.arange(8), np.array([], dtype=np.int64), np.arange(1, 8, 2)]
+    res = ph.track_batch([S, C, S], [g, gc, g], paths, ph.track_opts(prec=2, mixed=1))
+    off = res["path_off"]
+    assert list(off) == [0, 8, 8, 12]
+    with pytest.raises(ph.PHError, match="-1"):
+        ph.track_batch([S], [g], [np.array([3, 8])], ph.track_opts(prec=2, mixed=1))
+    alone = ph.track(S, g, 8, ph.track_opts(prec=2, mixed=1))
+    X = ph.from_soa(res["x_end"], 12, (8, 2, 2))
+    Xa = ph.from_soa(alone["x_end"], 8, (3, 2, 2))
+    assert np.all(res["status"] == 1)
+    assert np.array_equal(X[:8, :3], Xa) and np.array_equal(res["steps"][:8], alone["steps"])
