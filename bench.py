@@ -102,9 +102,15 @@ def cpu_baseline(sysm, L, x, t, gamma, target_s=15.0):
     t0 = time.perf_counter()
     oracle.eval_threaded(sysm, L, x[:npts], t[:npts], gamma, threads=threads)
     wall = time.perf_counter() - t0
+    # one core, the paper's convention, on a smaller sample (about 3 s)
+    m1 = int(max(1, min(len(t), 3.0 / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.eval_homotopy(sysm, L, x[:m1], t[:m1], gamma, scales=False)
+    one_rate = m1 / (time.perf_counter() - t0)
     return {"value": npts / wall, "unit": "points/s", "cores": threads, "kind": "oracle",
             "sample": f"first {npts} of the 65536 points, {PREC_NAME[L]}, {threads} host threads "
-                      f"over contiguous point ranges, {wall:.1f} s wall"}
+                      f"over contiguous point ranges, {wall:.1f} s wall; one core: first {m1} points",
+            "one_core_value": one_rate}
 
 
 def time_eval(ph, torch, S, sysm, L, npts, steps, warmup, gamma, rng=None):
