@@ -140,9 +140,10 @@ int ph_eval_set_config(ph_system *target, const ph_system *start, int32_t prec, 
                        int32_t waves, int32_t groups);
 
 /*
- * ph_eval_get_config -- the configuration pinned or tuned for (target, start,
- * prec) in this handle (all zero: automatic).  Host-only; PH_EINVAL on null
- * pointers.
+ * ph_eval_get_config -- the configuration ph_eval_jac would use for (target,
+ * start, prec): the one pinned or tuned in this handle, else the last entry
+ * for these systems in the PH_AUTOTUNE_CACHE file (which the handle then
+ * keeps); all zero: automatic.  Host-only; PH_EINVAL on null pointers.
  */
 int ph_eval_get_config(const ph_system *target, const ph_system *start, int32_t prec,
                        int32_t *kernel, int32_t *waves, int32_t *groups);

@@ -808,12 +808,12 @@ extern "C" int ph_eval_get_config(const ph_system *target, const ph_system *star
                                   int32_t *kernel, int32_t *waves, int32_t *groups)
 {
     if (!target || !kernel || !waves || !groups) return fail(PH_EINVAL, "null argument");
-    ph_system *tg = const_cast<ph_system *>(target);
-    std::lock_guard<std::mutex> lk(tg->mu);
-    auto it = tg->eval_cfg.find({start, prec});
-    *kernel = it == tg->eval_cfg.end() ? 0 : it->second.kernel;
-    *waves = it == tg->eval_cfg.end() ? 0 : it->second.W;
-    *groups = it == tg->eval_cfg.end() ? 0 : it->second.G;
+    // the same lookup ph_eval_jac makes: the handle, else the cache file
+    EvalCfg c{0, 0, 0};
+    if (!eval_cfg_lookup(target, start, prec, c)) c = EvalCfg{0, 0, 0};
+    *kernel = c.kernel;
+    *waves = c.W;
+    *groups = c.G;
     return PH_OK;
 }
 

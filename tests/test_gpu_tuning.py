@@ -125,6 +125,7 @@ def test_autotune_choice_persists_in_cache_file(tmp_path, monkeypatch):
     fields[4:7] = ["1", "1", "1"]
     cache.write_text(" ".join(fields) + "\n")
     S2 = ph.System(s)
+    assert ph.eval_get_config(S2, L) == (1, 1, 1)      # read back from the file
     v2, j2 = _eval(S2, s, L, x, t, g)
     assert max(scaled_error(v2[idx], ov, sv), scaled_error(j2[idx], oj, sj)) <= TOL[L]
     # and an entry asking for a kernel that cannot run is honoured (and refused)
