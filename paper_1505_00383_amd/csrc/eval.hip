@@ -431,23 +431,28 @@ __device__ __forceinline__ DHead dfast_head(const DTerm *__restrict__ r)
 // One term with exactly K factors, the first M of them with exponent >= 2
 // (the host sorts factors by exponent and groups records by (K, M)), with
 // the products of Table 6 reordered for instruction-level parallelism: all
-// coordinates and powers are read from LDS first; the suffix products
-// x_l ... x_{K-1} do not depend on the common factor and form a second
-// dependency chain beside the forward products; the M powers x^(a-1) are
-// multiplied into the coefficient by a balanced tree.  3K - 3 + M complex
-// products, the cost model's count.  The head of the NEXT record (same
-// group) is fetched once the forward chain is done.
+// coordinates and powers are read from LDS first, and the head of the NEXT
+// record (same group) is fetched right after; the suffix products
+// x_l ... x_{K-1} do not depend on the common factor and form a chain of
+// their own; the M powers x^(a-1) are multiplied into the coefficient by a
+// balanced tree; then one forward pass carries the running prefix product
+// and issues, at each factor, the cross product with the suffix beside the
+// next prefix product, so that only one prefix product is ever live.
+// 3K - 3 + M complex products, the cost model's count.  A term's factors
+// are distinct unknowns, so the order of its row updates does not change
+// any result.
 template <int K, int M, class Row>
 __device__ __forceinline__ void dfast_sweep(const DHead &h, const DTerm *__restrict__ rnext, DHead &hnext,
                                             const char *__restrict__ xb, int lane, C<1> cf,
                                             Row &row, C<1> &v)
 {
-    C<1> xv[K], pw[M > 0 ? M : 1], sf[K], q[K];
+    C<1> xv[K], pw[M > 0 ? M : 1], sf[K];
 #pragma unroll
     for (int l = 0; l < K; ++l) xv[l] = ldsc(xb, (h.w[l] & 0xffffu) * 512u, lane);
     // the first M factors (a >= 2) take x^(a-1) from the power table
 #pragma unroll
     for (int l = 0; l < M; ++l) pw[l] = ldsc(xb, (h.w[l] >> 16) * 8u, lane);
+    hnext = dfast_head<K>(rnext);
     // suffix products: sf[l] = x_l x_{l+1} ... x_{K-1}
     sf[K - 1] = xv[K - 1];
 #pragma unroll
@@ -461,14 +466,16 @@ __device__ __forceinline__ void dfast_sweep(const DHead &h, const DTerm *__restr
         }
         cf = c_mul<1>(cf, pw[0]);
     }
-    q[0] = cf;
+    // q = c x_0 ... x_{l-1} (times the powers); partial l = q * sf[l+1]
+    C<1> q = cf;
 #pragma unroll
-    for (int l = 1; l < K; ++l) q[l] = c_mul<1>(q[l - 1], xv[l - 1]);
-    v = c_add<1>(v, c_mul<1>(q[K - 1], xv[K - 1]));
-    hnext = dfast_head<K>(rnext);
-    row.fma((int)(h.w[K - 1] & 0xffffu), h.a[K - 1], q[K - 1]);
-#pragma unroll
-    for (int l = K - 2; l >= 0; --l) row.fma((int)(h.w[l] & 0xffffu), h.a[l], c_mul<1>(q[l], sf[l + 1]));
+    for (int l = 0; l < K - 1; ++l) {
+        const C<1> part = c_mul<1>(q, sf[l + 1]);
+        q = c_mul<1>(q, xv[l]);
+        row.fma((int)(h.w[l] & 0xffffu), h.a[l], part);
+    }
+    v = c_add<1>(v, c_mul<1>(q, xv[K - 1]));
+    row.fma((int)(h.w[K - 1] & 0xffffu), h.a[K - 1], q);
 }
 
 // All records of one equation, group by group: (K, M) = (1,0), (1,1), (2,0),
