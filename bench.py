@@ -45,18 +45,20 @@ PREC_NAME = {1: "complex double", 2: "complex double double", 4: "complex quad d
 TRAFFIC = {
     # the double kernel writes H and J once whatever its tiling
     "eval_d_pinned_kernel": {
-        "bytes": 39273813 + 1107450027,   # read + write
-        "sources": {"paper_1505_00383_amd/csrc/eval.hip": "2a2ffd339db37cfd",
+        "bytes": 41472341 + 1107454677,   # read + write
+        "sources": {"paper_1505_00383_amd/csrc/eval.hip": "79c12cb91e08a0a4",
                     "paper_1505_00383_amd/csrc/ph_arith.hpp": "f4b035f2f8fac960",
-                    "paper_1505_00383_amd/csrc/system.cpp": "52b8fab09dd1b29d"},
+                    "paper_1505_00383_amd/csrc/system.cpp": "3d93137455c433f0",
+                    "paper_1505_00383_amd/csrc/ph_internal.hpp": "f7f85e81b4728b64"},
     },
     # the general kernel's re-reads depend on its tiling: valid for this one
     "eval_kernel<2,8,true,true>": {
-        "bytes": 29135460053 + 34254765013,
+        "bytes": 29130984363 + 34249580075,
         "launch": (1, 8, 4),
-        "sources": {"paper_1505_00383_amd/csrc/eval.hip": "2a2ffd339db37cfd",
+        "sources": {"paper_1505_00383_amd/csrc/eval.hip": "79c12cb91e08a0a4",
                     "paper_1505_00383_amd/csrc/ph_arith.hpp": "f4b035f2f8fac960",
-                    "paper_1505_00383_amd/csrc/system.cpp": "52b8fab09dd1b29d"},
+                    "paper_1505_00383_amd/csrc/system.cpp": "3d93137455c433f0",
+                    "paper_1505_00383_amd/csrc/ph_internal.hpp": "f7f85e81b4728b64"},
     },
 }
 

@@ -415,11 +415,11 @@ struct PinRow16 {
 struct DHead {
     double cre, cim;
     int sel;
-    uint32_t w[8];
+    uint32_t xo[8], po[8], j2[8];
     double a[8];
 };
 
-template <int K>
+template <int K, int M>
 __device__ __forceinline__ DHead dfast_head(const DTerm *__restrict__ r)
 {
     DHead h;
@@ -427,7 +427,11 @@ __device__ __forceinline__ DHead dfast_head(const DTerm *__restrict__ r)
     h.cim = r->cim;
     h.sel = r->sel;
 #pragma unroll
-    for (int l = 0; l < K; ++l) h.w[l] = r->w[l];
+    for (int l = 0; l < K; ++l) h.xo[l] = r->xo[l];
+#pragma unroll
+    for (int l = 0; l < M; ++l) h.po[l] = r->po[l];
+#pragma unroll
+    for (int l = 0; l < K; ++l) h.j2[l] = r->j2[l];
 #pragma unroll
     for (int l = 0; l < K; ++l) h.a[l] = r->a[l];
     return h;
@@ -453,11 +457,11 @@ __device__ __forceinline__ void dfast_sweep(const DHead &h, const DTerm *__restr
 {
     C<1> xv[K], pw[M > 0 ? M : 1], sf[K];
 #pragma unroll
-    for (int l = 0; l < K; ++l) xv[l] = ldsc(xb, (h.w[l] & 0xffffu) * 512u, lane);
+    for (int l = 0; l < K; ++l) xv[l] = ldsc(xb, h.xo[l], lane);
     // the first M factors (a >= 2) take x^(a-1) from the power table
 #pragma unroll
-    for (int l = 0; l < M; ++l) pw[l] = ldsc(xb, (h.w[l] >> 16) * 8u, lane);
-    hnext = dfast_head<K>(rnext);
+    for (int l = 0; l < M; ++l) pw[l] = ldsc(xb, h.po[l], lane);
+    hnext = dfast_head<K, M>(rnext);
     // suffix products: sf[l] = x_l x_{l+1} ... x_{K-1}
     sf[K - 1] = xv[K - 1];
 #pragma unroll
@@ -477,10 +481,10 @@ __device__ __forceinline__ void dfast_sweep(const DHead &h, const DTerm *__restr
     for (int l = 0; l < K - 1; ++l) {
         const C<1> part = c_mul<1>(q, sf[l + 1]);
         q = c_mul<1>(q, xv[l]);
-        row.fma((int)(h.w[l] & 0xffffu), h.a[l], part);
+        row.fma((int)h.j2[l], h.a[l], part);
     }
     v = c_add<1>(v, c_mul<1>(q, xv[K - 1]));
-    row.fma((int)(h.w[K - 1] & 0xffffu), h.a[K - 1], q);
+    row.fma((int)h.j2[K - 1], h.a[K - 1], q);
 }
 
 // All records of one equation, group by group: (K, M) = (1,0), (1,1), (2,0),
@@ -493,7 +497,7 @@ __device__ __forceinline__ void dfast_groups(const int32_t *__restrict__ run, co
     constexpr int g = drun_group(K, M);
     const int s0 = run[g], s1 = run[g + 1];
     if (s0 < s1) {
-        DHead h = dfast_head<K>(dterm + s0);
+        DHead h = dfast_head<K, M>(dterm + s0);
         for (int s = s0; s < s1; ++s) {
             const DTerm *rn = dterm + (s + 1 < s1 ? s + 1 : s);
             const C<1> c0 = c_from<1>(h.cre, h.cim);

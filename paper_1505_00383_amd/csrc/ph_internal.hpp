@@ -37,11 +37,12 @@ int hip_fail(hipError_t e, const char *what);
 // on its own point (Section 3: all threads of a block evaluate the same
 // monomial at different points).
 // Term record of the complex-double fast path: everything one term needs in
-// one 128-byte block read through scalar loads.  w[l] = 2 * variable (bits
-// 0..15, the register index of its Jacobian column) and LDS byte offset of
-// x_{j_l}^{a_l - 1} divided by 8 (bits 16..31; powers x, x^2, x^3 and a row
-// of ones are staged per point), a[l] the exponent as a double (folded into
-// the FMA that accumulates the partial).
+// one 192-byte block read through scalar loads, each field ready to use so
+// that the kernel spends no scalar instructions decoding it: per factor l the
+// LDS byte offsets of x_{j_l} and of x_{j_l}^{a_l - 1} (powers x, x^2, x^3
+// and a row of ones are staged per point), the register index 2 j_l of its
+// Jacobian column, and the exponent a_l as a double (folded into the FMA that
+// accumulates the partial).
 // Fast-path record groups: (k, m) with 0 <= m <= k <= 8, numbered k(k+1)/2 + m;
 // DRUN offsets per equation (45 groups and the end).
 constexpr int DRUN = 46;
@@ -50,10 +51,12 @@ inline constexpr int drun_group(int k, int m) { return k * (k + 1) / 2 + m; }
 struct DTerm {
     double cre, cim;
     int32_t k;
-    int32_t sel;    // bit 0: start term; bits 8..11: factors with a >= 3; 16..19: with a >= 2
-    uint32_t w[8];  // 2 * variable | (LDS offset of x^(a-1), or of the ones row, / 8) << 16
+    int32_t sel;     // bit 0: start term; bits 8..11: factors with a >= 3; 16..19: with a >= 2
+    uint32_t xo[8];  // LDS byte offset of the factor's coordinate x_v (v * 1024)
+    uint32_t po[8];  // LDS byte offset of x_v^(a-1), or of the ones row for a = 1
+    uint32_t j2[8];  // 2 * v: register index of column v in the pinned row
+    double a[8];     // exponents
     int32_t pad[2];
-    double a[8];
 };
 
 struct DevTable {

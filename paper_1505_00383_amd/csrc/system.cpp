@@ -159,7 +159,9 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
                 for (int l = 0; l < r.k; ++l) {
                     const int q = ord[l], v = sy.fac_var[q], e = sy.fac_exp[q];
                     const uint32_t poff = e == 1 ? ones_off : uint32_t(((e - 2) * nv + v) * 2 * 64 * 8);
-                    r.w[l] = uint32_t(2 * v) | ((poff / 8) << 16);
+                    r.xo[l] = uint32_t(v) * 2u * 64u * 8u;
+                    r.po[l] = poff;
+                    r.j2[l] = uint32_t(2 * v);
                     r.a[l] = double(e);
                     m3 += e >= 3;
                     m2 += e >= 2;
