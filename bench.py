@@ -368,6 +368,9 @@ def profile_mode(ph, torch, mode):
                           "copies": 3, "copy_GBps_read_plus_write": 2 * n * 8 / copy_s / 1e9,
                           "fill_GBps_write": n * 8 / fill_s / 1e9}))
         return
+    if mode == "eval_hbm":
+        print(json.dumps({"mode": mode, **hbm_extra(ph, torch, 20)}))
+        return
     if mode == "track_n16_qd":
         s = synth.tracking_quadratic16()
         res = ph.track(ph.System(s), synth.gamma_of(s), 2 ** 16, ph.track_opts(prec=4, mixed=1))
@@ -393,10 +396,11 @@ def main():
     ap.add_argument("--kernel", type=int, default=0,
                     help="evaluation kernel choice of ph_eval_set_config for the timed launches "
                          "(0 automatic; 5 the unfused three-kernel design)")
-    ap.add_argument("--mode", default="eval", choices=["eval", "track_n16_qd", "track_batch", "copy"],
+    ap.add_argument("--mode", default="eval", choices=["eval", "eval_hbm", "track_n16_qd", "track_batch", "copy"],
                     help="eval: the benchmark line; the others run one workload for profiling: "
-                         "the 65536-path QD-mixed tracking, the 64-system batch, or a device "
-                         "copy of 2 GiB (calibrates the HBM byte counters)")
+                         "the HBM-bound n = 16 evaluation at 2^20 points, the 65536-path QD-mixed "
+                         "tracking, the 64-system batch, or a device copy of 2 GiB (calibrates "
+                         "the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): paths and "
