@@ -244,6 +244,44 @@ def hbm_extra(ph, torch, steps):
             "hbm_frac_compulsory": bpp * npts / (ms * 1e-3) / PEAK_HBM, "finite": ok}
 
 
+def pcie_extra(ph, torch, S, sysm, L, npts, gamma, reps=5):
+    """The rate a caller holding its points in host memory sees: copy x and t
+    from pinned host buffers, evaluate, copy H and J back, all on one stream.
+    Not the benchmark value (that one starts with the inputs in HBM)."""
+    from paper_1505_00383_amd import synth
+    x, t = synth.torus_points(sysm, npts, L)
+    xs_host = ph.to_soa(x, device="cpu").pin_memory()
+    t_host = torch.as_tensor(t, dtype=torch.float64).pin_memory()
+    xs = torch.empty_like(xs_host, device="cuda")
+    tt = torch.empty_like(t_host, device="cuda")
+    val = torch.empty((sysm.n_eq * 2 * L, npts), dtype=torch.float64, device="cuda")
+    jac = torch.empty((sysm.n_eq * sysm.n_var * 2 * L, npts), dtype=torch.float64, device="cuda")
+    val_host = torch.empty(val.shape, dtype=torch.float64, pin_memory=True)
+    jac_host = torch.empty(jac.shape, dtype=torch.float64, pin_memory=True)
+
+    def one():
+        xs.copy_(xs_host, non_blocking=True)
+        tt.copy_(t_host, non_blocking=True)
+        ph.eval_jac(S, xs, npts, L, tt, gamma, val=val, jac=jac)
+        val_host.copy_(val, non_blocking=True)
+        jac_host.copy_(jac, non_blocking=True)
+
+    one()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        one()
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    moved = xs_host.numel() * 8 + t_host.numel() * 8 + val.numel() * 8 + jac.numel() * 8
+    return {"points": npts, "ms": ms, "points_per_s": npts / (ms * 1e-3),
+            "bytes_over_pcie": moved, "GBps_over_pcie_incl_eval": moved / (ms * 1e-3) / 1e9,
+            "finite": bool(torch.isfinite(jac_host).all())}
+
+
 # The paper's own speedups of its GPU evaluation over one CPU core (Tables
 # of Section 4, a Tesla K20C against one core of a Xeon E5-2670): context for
 # the stand-ins of the same shape, not a target.
@@ -499,6 +537,7 @@ def main():
                                         "fp64_frac": f2 * npts / (ms2 * 1e-3) / PEAK_FP64,
                                         "launch": cfg2, "finite": ok2}
         extras["eval_n16_d2_hbm_1M_points_double"] = hbm_extra(ph, torch, max(3, args.steps // 4))
+        extras["eval_pcie_inclusive_host_buffers"] = pcie_extra(ph, torch, S, sysm, L, npts, gamma)
         extras["unfused_three_kernel_ablation"] = unfused_extra(ph, torch, S, sysm, gamma, 5)
         extras.update(tracking_extras(ph, torch))
         extras["track_batch64_dd_mixed"] = batch_extra(ph, torch)
