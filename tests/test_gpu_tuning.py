@@ -95,6 +95,48 @@ def test_inapplicable_kernel_is_refused():
         ph.eval_set_config(S, 1, 7)
 
 
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_full_workload_every_launch_the_autotuner_may_pick(L):
+    """The benchmark times the autotuner's choice on the full workload (n = 32,
+    64 terms of 8 factors per equation, 65536 points): every (kernel, waves,
+    groups) the autotuner can pick, at that size, against the oracle on a
+    sample of points including both ends of the first tile and the last point."""
+    import torch
+    s = synth.eval_dense()
+    npts = 65536
+    x, t = synth.torus_points(s, npts, L)
+    g = synth.gamma_of(s)
+    S = ph.System(s)
+    xs = ph.to_soa(x)
+    tt = torch.as_tensor(t, dtype=torch.float64).cuda()
+    nsamp = {1: 8, 2: 4, 4: 2}[L]
+    idx = np.unique(np.concatenate([[0, 63, npts - 1],
+                                    np.random.default_rng(21).integers(0, npts, nsamp)]))
+    ov, oj, sv, sj = oracle.eval_homotopy(s, L, x[idx], t[idx], g)
+    it = torch.as_tensor(idx, device="cuda")
+    checked = 0
+    for k in (ph.EVAL_FAST, ph.EVAL_FAST_VECROW, ph.EVAL_REGROW, ph.EVAL_GENERAL):
+        for W in (1, 2, 4, 6, 8):
+            for G in (1, 2, 4, 8):
+                if W * G > s.n_eq:
+                    continue
+                ph.eval_set_config(S, L, k, W, G)
+                try:
+                    val, jm = ph.eval_jac(S, xs, npts, L, tt, g)
+                except ph.PHError as e:
+                    assert "-4" in str(e)            # the kernel does not apply here
+                    continue
+                torch.cuda.synchronize()
+                v = val[:, it].T.contiguous().cpu().numpy().reshape(len(idx), s.n_eq, 2, L)
+                j = jm[:, it].T.contiguous().cpu().numpy().reshape(len(idx), s.n_eq, s.n_var, 2, L)
+                e = max(scaled_error(v, ov, sv), scaled_error(j, oj, sj))
+                assert e <= TOL[L], (k, W, G, e)
+                checked += 1
+    ph.eval_set_config(S, L)
+    assert checked >= 18 * (3 if L == 1 else 1)    # 18 tilings per applicable kernel
+    print(f"[gpu] L={L} full workload, {checked} launch configurations match the oracle", flush=True)
+
+
 def test_autotune_choice_persists_in_cache_file(tmp_path, monkeypatch):
     cache = tmp_path / "tune.txt"
     monkeypatch.setenv("PH_AUTOTUNE_CACHE", str(cache))
