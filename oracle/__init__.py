@@ -17,10 +17,14 @@ Parity status of every exported function (what pins it, in ``tests/``):
 * ``mgs``                        -- pinned: ``numpy.linalg.lstsq``, mpmath QR at
   high precision, orthonormality of Q, the singular flag.
 * ``start_solution``             -- pinned: closed form, x_i^{d_i} = 1 in Fraction.
-* ``track_path`` / ``track``     -- pinned: f = g invariance, decoupled closed
-  form, n = 1 against ``numpy.roots``, Bezout count with distinct endpoints,
-  endpoint residuals, forced failures.  The step sequence itself is parity
-  unpinned (only endpoints are pinned).
+* ``track_path`` / ``track``     -- pinned: f = g invariance (total-degree and
+  explicit start systems, L = 1, 2, 4), decoupled closed form (to 1e-9 in D/DD,
+  to 1e-50 against 80-digit mpmath roots in QD, plain and mixed), n = 1 against
+  ``numpy.roots``, Bezout count with distinct endpoints, endpoint residuals
+  (<= 256 u_L S, L = 1, 2, 4), mixed vs plain agreement (1e-24 DD, 1e-48 QD),
+  endpoints independent of the start system, the residual half of the
+  convergence test, the endpoint check after the polish, forced failures.
+  The step sequence itself is parity unpinned (only endpoints are pinned).
 """
 from __future__ import annotations
 
@@ -73,7 +77,8 @@ def lib():
         L.ora_mgs.restype = i32
         L.ora_start_solution.argtypes = [i32, i32, P, i64, P]
         L.ora_start_solution.restype = i32
-        L.ora_track_path.argtypes = [i32, P, i32, i32, P, P, P, P, P, P, P, P, P, P, P, P]
+        L.ora_track_path.argtypes = [i32, P, i32, i32, P, P, P, P, P, i32, P, P, P, P, P, P, P, P,
+                                     P, P, P, P]
         L.ora_extrapolate.argtypes = [i32, i32, i32, P, P, ctypes.c_double, P]
         L.ora_track_path.restype = i32
         _lib = L
@@ -218,6 +223,7 @@ class Opts:
     diverge_norm: float = 1e8
     polish_tol: float = -1.0  # < 0 selects 8 u_L
     max_steps: int = 100_000
+    tol_res: float = 1e-6     # residual test ||H|| <= tol_res ||J||_F max(1, ||x||)
 
 
 class _COpts(ctypes.Structure):
@@ -228,7 +234,7 @@ class _COpts(ctypes.Structure):
                 ("h_max", ctypes.c_double), ("shrink", ctypes.c_double),
                 ("expand", ctypes.c_double), ("tol_dx", ctypes.c_double),
                 ("diverge_norm", ctypes.c_double), ("polish_tol", ctypes.c_double),
-                ("max_steps", ctypes.c_int64)]
+                ("max_steps", ctypes.c_int64), ("tol_res", ctypes.c_double)]
 
 
 def unit_roundoff(L: int) -> float:
@@ -253,31 +259,39 @@ def extrapolate(L: int, T, X, t1: float):
     return out
 
 
-def track_path(s, gamma, x0, opts: Opts):
-    """Track one path of gamma(1-t)g + t f from the start point x0 [n,2,L]."""
+def track_path(s, gamma, x0, opts: Opts, start=None):
+    """Track one path of gamma(1-t)g + t f from the start point x0 [n,2,L];
+    g is ``start`` or, when None, the total-degree start system x_i^{d_i} - 1."""
     L = opts.prec
     x = _c(x0, np.float64).copy()
     assert x.shape == (s.n_var, 2, L)
     arrs = _sys_args(s)
+    garrs = _sys_args(start) if start is not None else (None,) * 5
     g = np.array([complex(gamma).real, complex(gamma).imag])
     reason = ctypes.c_int32(0)
     steps, rej, newt = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int64(0)
     tend = ctypes.c_double(0.0)
     co = _copts(opts)
-    st = lib().ora_track_path(L, ctypes.byref(co), s.n_eq, s.n_var, *[_p(a) for a in arrs], _p(g),
+    st = lib().ora_track_path(L, ctypes.byref(co), s.n_eq, s.n_var, *[_p(a) for a in arrs],
+                              1 if start is not None else 0, *[_p(a) for a in garrs], _p(g),
                               _p(x), ctypes.byref(reason), ctypes.byref(steps), ctypes.byref(rej),
                               ctypes.byref(newt), ctypes.byref(tend))
     return dict(x=x, status=int(st), reason=int(reason.value), steps=int(steps.value),
                 rejected=int(rej.value), newton=int(newt.value), t=float(tend.value))
 
 
-def track(s, gamma, paths, opts: Opts, threads: int = 1):
-    """Track the listed start-path indices of the total-degree homotopy.
-    Returns x [npaths, n, 2, L], status, reason, steps, newton arrays."""
+def track(s, gamma, paths, opts: Opts, threads: int = 1, start=None, x0=None):
+    """Track paths of gamma(1-t) g + t f.  With ``start`` None, ``paths`` lists
+    start-solution indices of the total-degree start system (roots of unity);
+    with a start system g, ``x0`` [npaths, n, 2, L] holds its start points and
+    ``paths`` only counts them.  Returns x [npaths, n, 2, L], status, reason,
+    steps, newton arrays."""
     L = opts.prec
     deg = degrees(s)
     paths = np.asarray(paths, dtype=np.int64)
     npaths = len(paths)
+    if start is not None:
+        assert x0 is not None and len(x0) == npaths
     X = np.zeros((npaths, s.n_var, 2, L))
     status = np.zeros(npaths, dtype=np.int8)
     reason = np.zeros(npaths, dtype=np.int8)
@@ -285,7 +299,8 @@ def track(s, gamma, paths, opts: Opts, threads: int = 1):
     newton = np.zeros(npaths, dtype=np.int64)
 
     def work(k):
-        r = track_path(s, gamma, start_solution(L, deg, int(paths[k])), opts)
+        xs = x0[k] if x0 is not None else start_solution(L, deg, int(paths[k]))
+        r = track_path(s, gamma, xs, opts, start=start)
         X[k] = r["x"]
         status[k] = r["status"]
         reason[k] = r["reason"]

@@ -694,6 +694,7 @@ typedef struct {
     int32_t prec, mixed, predictor_order, max_newton, expand_after, polish_max;
     double h_init, h_min, h_max, shrink, expand, tol_dx, diverge_norm, polish_tol;
     int64_t max_steps;
+    double tol_res;
 } ora_opts;
 
 enum { R_NONE = 0, R_SUCCESS = 1, R_DIVERGED = 2, R_STEP_UNDERFLOW = 3, R_MAX_STEPS = 4,
@@ -719,12 +720,22 @@ static int has_nan(int n, const cx *x)
 }
 
 /* One Newton step at (x, t): solve J dx = -H by MGS (FP64 when mixed, else
- * L limbs) and return dx.  Returns 1 when MGS flags the matrix singular. */
+ * L limbs) and return dx.  Returns 1 when MGS flags the matrix singular.
+ * hres (nullable) receives ||H(x, t)||_inf and jfro (nullable) ||J||_F, both
+ * from the leading limbs in FP64: the residual at the point where the Newton
+ * system is formed, and the scale it is compared against. */
 static int newton_step(int L, int mixed, const sysv *f, const sysv *g, const int32_t *deg, cx gamma,
-                       int has_t, double t, const cx *x, cx *dx, cx *hv, cx *jm, cx *w)
+                       int has_t, double t, const cx *x, cx *dx, cx *hv, cx *jm, cx *w,
+                       double *hres, double *jfro)
 {
     int n = f->n_var, m = f->n_eq;
     eval_homotopy(L, f, g, deg, gamma, has_t, t, x, hv, jm, NULL, NULL);
+    if (hres) *hres = norm_inf(m, hv);
+    if (jfro) {
+        double s = 0.0;
+        for (int k = 0; k < m * n; ++k) s += jm[k].re.v[0] * jm[k].re.v[0] + jm[k].im.v[0] * jm[k].im.v[0];
+        *jfro = sqrt(s);
+    }
     int Ls = mixed ? 1 : L;
     for (int i = 0; i < m; ++i) {
         for (int j = 0; j < n; ++j) {
@@ -796,25 +807,36 @@ void ora_extrapolate(int L, int m, int n, const double *T, const double *X, doub
 }
 
 /*
- * Track one path from x (start solution, t = 0) to t = 1.  Step control:
- * h <- min(h, 1 - t); predict (with predictor_order 1 the secant through
- * the last two accepted points; with order m >= 2 the extrapolation above
- * through the current point and up to m previous accepted points, the secant
- * while only one previous point exists; the current point on the first
- * step); correct with at most max_newton
- * Newton steps, converged when ||dx|| <= tol_dx max(1, ||x||), failed when a
- * later step does not shrink the update or MGS is singular.  Accepted steps
+ * Track one path from x (a start solution of g, t = 0) to t = 1 (Section 2).
+ * Step control: h <- min(h, 1 - t); predict (with predictor_order 1 the
+ * secant through the last two accepted points; with order m >= 2 the
+ * extrapolation above through the current point and up to m previous
+ * accepted points, the secant while only one previous point exists; the
+ * current point on the first step); then evaluate-correct with at most
+ * max_newton Newton steps.  Section 2 ends the corrector when both the
+ * residuals and the size of the updates are small: a step converges when
+ * ||dx|| <= tol_dx max(1, ||x||) and the residual at the point where the
+ * Newton system was formed satisfies ||H|| <= tol_res ||J||_F max(1, ||x||)
+ * (x the updated point, every norm in FP64 from the leading limbs); it fails
+ * when a later update does not shrink or MGS is singular.  Accepted steps
  * advance t and count toward expansion of h (x expand after expand_after
  * successes, capped by h_max); rejected ones shrink h and fail below h_min.
- * At t = 1 the endpoint is polished by Newton on f in the residual precision.
+ * At t = 1 the endpoint is polished by Newton on f in the residual precision
+ * (a non-finite update is never applied); a polished endpoint that is not
+ * finite, or lies beyond diverge_norm, ends the path as a failure.
+ * g_present = 0 selects the total-degree start system g_i = x_i^{d_i} - 1.
  */
 int ora_track_path(int L, const ora_opts *o, int n_eq, int n_var, const int32_t *eq_term_off,
                    const int32_t *term_fac_off, const int32_t *fac_var, const int32_t *fac_exp,
-                   const double *coef, const double *gamma, double *x_io /* [n][2][L] */,
-                   int32_t *reason_out, int64_t *steps_out, int64_t *rejected_out,
-                   int64_t *newton_out, double *t_out)
+                   const double *coef, int g_present, const int32_t *g_eq_term_off,
+                   const int32_t *g_term_fac_off, const int32_t *g_fac_var,
+                   const int32_t *g_fac_exp, const double *g_coef, const double *gamma,
+                   double *x_io /* [n][2][L] */, int32_t *reason_out, int64_t *steps_out,
+                   int64_t *rejected_out, int64_t *newton_out, double *t_out)
 {
     sysv f = {n_eq, n_var, eq_term_off, term_fac_off, fac_var, fac_exp, coef};
+    sysv gs = {n_eq, n_var, g_eq_term_off, g_term_fac_off, g_fac_var, g_fac_exp, g_coef};
+    const sysv *g = g_present ? &gs : NULL;
     int n = n_var, m = n_eq;
     int32_t *deg = (int32_t *)malloc(sizeof(int32_t) * m);
     sys_degrees(&f, deg);
@@ -863,12 +885,14 @@ int ora_track_path(int L, const ora_opts *o, int n_eq, int n_var, const int32_t 
         double dprev = 0.0;
         for (int it = 1; it <= o->max_newton; ++it) {
             newton++;
-            sing = newton_step(L, o->mixed, &f, NULL, deg, gam, 1, t1, xh, dx, hv, jm, w);
+            double hres = 0.0, jfro = 0.0;
+            sing = newton_step(L, o->mixed, &f, g, deg, gam, 1, t1, xh, dx, hv, jm, w, &hres, &jfro);
             if (sing) break;
             for (int j = 0; j < n; ++j) xh[j] = cx_add(L, xh[j], dx[j]);
             double dn = norm_inf(n, dx), xn = norm_inf(n, xh);
             if (isnan(dn) || isnan(xn)) break;
-            if (dn <= o->tol_dx * (xn > 1.0 ? xn : 1.0)) {
+            const double sx = xn > 1.0 ? xn : 1.0;
+            if (dn <= o->tol_dx * sx && hres <= o->tol_res * jfro * sx) {
                 conv = 1;
                 break;
             }
@@ -913,12 +937,14 @@ int ora_track_path(int L, const ora_opts *o, int n_eq, int n_var, const int32_t 
     }
     if (reason == R_SUCCESS) {
         /* polish at t = 1: Newton on f until ||dx|| <= polish_tol max(1,||x||)
-         * or the update stops halving, at most polish_max steps */
+         * or the update stops halving, at most polish_max steps; an update
+         * that is not finite ends the polish without being applied */
         double dprev = INFINITY;
         for (int it = 0; it < o->polish_max; ++it) {
-            int sing = newton_step(L, o->mixed, &f, NULL, deg, gam, 0, 1.0, x, dx, hv, jm, w);
+            int sing = newton_step(L, o->mixed, &f, g, deg, gam, 0, 1.0, x, dx, hv, jm, w, NULL, NULL);
             if (sing) break;
             double dn = norm_inf(n, dx);
+            if (!isfinite(dn)) break;
             if (!(dn < 0.5 * dprev) && it > 0) break;
             for (int j = 0; j < n; ++j) x[j] = cx_add(L, x[j], dx[j]);
             newton++;
@@ -926,6 +952,9 @@ int ora_track_path(int L, const ora_opts *o, int n_eq, int n_var, const int32_t 
             if (dn <= o->polish_tol * (xn > 1.0 ? xn : 1.0)) break;
             dprev = dn;
         }
+        /* the endpoint must be finite and within diverge_norm */
+        if (has_nan(n, x)) reason = R_NAN;
+        else if (norm_inf(n, x) > o->diverge_norm) reason = R_DIVERGED;
     }
     for (int j = 0; j < n; ++j) store_cx(x_io + (size_t)j * 2 * L, L, x[j]);
     if (reason_out) *reason_out = reason;

@@ -19,7 +19,7 @@ import pytest
 
 import oracle
 from paper_1505_00383_amd import synth
-from tests.exact import frc
+from tests.exact import frc, limb_sum_diff
 
 U = {1: 2.0 ** -53, 2: 2.0 ** -104, 4: 2.0 ** -208}
 
@@ -232,3 +232,198 @@ def test_extrapolation_order_one_is_the_secant():
     r = (0.55 - 0.4) / (0.4 - 0.3)
     ref = complex(1.25, -0.5) + r * (complex(1.25, -0.5) - complex(0.75, 0.25))
     assert abs(complex(got[0, 0].sum(), got[0, 1].sum()) - ref) <= 1e-15
+
+
+# ---------------------------------------------------------------------------
+# Quad double (L = 4): the tracker's own pins at QD accuracy
+# ---------------------------------------------------------------------------
+def _mpc_of(limbs_cx):
+    """exact value of a [2][L] limb complex as an mpmath number (working
+    precision set by the caller)."""
+    import mpmath
+    re, im = frc(limbs_cx)
+    return mpmath.mpc(mpmath.mpf(re.numerator) / re.denominator,
+                      mpmath.mpf(im.numerator) / im.denominator)
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_decoupled_closed_form_quad_double(mixed):
+    """f_i = x_i^{d_i} - c_i at L = 4: every endpoint is the d_i-th root of c_i
+    on the branch continued from its start point (Section 2's paths), to
+    1e-50 relative.  The branch is chosen by the FP64 unwrapped continuation;
+    the root itself is computed by mpmath at 80 digits from the exact FP64
+    value of c_i, so the reference owes nothing to the oracle's arithmetic."""
+    import mpmath
+    mpmath.mp.dps = 80
+    rng = np.random.default_rng(23)
+    n = 3
+    deg = np.array([3, 2, 3], dtype=np.int32)
+    cs = [0.5 * synth.unit_complex(rng) * (1 + rng.uniform()) for _ in range(n)]
+    s = synth.system_from_terms(n, [[(1, {i: int(deg[i])}), (-cs[i], {})] for i in range(n)])
+    gamma = synth.unit_complex(rng)
+    B = int(np.prod(deg))
+    r = oracle.track(s, gamma, range(B), oracle.Opts(prec=4, mixed=mixed))
+    assert np.all(r["status"] == 1)
+    worst = 0.0
+    for p in range(B):
+        x0 = _cx(oracle.start_solution(1, deg, p))
+        for i in range(n):
+            approx = _branch_endpoint(gamma, cs[i], int(deg[i]), x0[i])
+            c = mpmath.mpc(cs[i].real, cs[i].imag)
+            d = int(deg[i])
+            roots = [mpmath.root(c, d, m) for m in range(d)]   # all d-th roots
+            ref = min(roots, key=lambda z: abs(complex(z) - approx))
+            got = _mpc_of(r["x"][p, i])
+            err = float(abs(got - ref) / max(1, abs(ref)))
+            worst = max(worst, err)
+            assert err <= 1e-50, (p, i, err)
+    print(f"decoupled QD mixed={mixed}: worst relative endpoint error {worst:.1e}")
+
+
+def test_f_equals_g_paths_stay_put_quad_double():
+    n = 3
+    deg = [2, 3, 2]
+    s = synth.system_from_terms(n, [[(1, {i: deg[i]}), (-1, {})] for i in range(n)])
+    gamma = complex(np.cos(1.1), np.sin(1.1))
+    r = oracle.track(s, gamma, range(12), oracle.Opts(prec=4))
+    assert np.all(r["status"] == 1)
+    for p in range(12):
+        x0 = oracle.start_solution(4, np.array(deg, dtype=np.int32), p)
+        d = np.abs(limb_sum_diff(r["x"][p], x0)).max()
+        assert d <= 1e-60, (p, d)
+
+
+def test_quad_double_residual_and_mixed_agreement():
+    """The n = 3, degree-2 workload at L = 4: 8 distinct endpoints, residual
+    |f(x*)| <= 256 u_QD S at every polished endpoint (polish target 8 u_QD),
+    and the mixed scheme (FP64 Newton solves) ends within 1e-48 of the plain
+    quad-double track."""
+    s = synth.tracking_small()
+    g = synth.gamma_of(s)
+    plain = oracle.track(s, g, range(8), oracle.Opts(prec=4, mixed=0))
+    mixed = oracle.track(s, g, range(8), oracle.Opts(prec=4, mixed=1))
+    assert np.all(plain["status"] == 1) and np.all(mixed["status"] == 1)
+    assert _residual_ok(s, plain, 4) and _residual_ok(s, mixed, 4)
+    E = _cx(plain["x"])
+    for a in range(8):
+        for b in range(a + 1, 8):
+            assert np.max(np.abs(E[a] - E[b])) > 1e-6
+    d = np.abs(limb_sum_diff(plain["x"], mixed["x"])).max()
+    assert d <= 1e-48 * max(1.0, np.abs(E).max()), d
+
+
+def test_singular_flag_quad_double():
+    """At x = 0 the Jacobian of x_i^2 - 1 and of the start system vanish: the
+    quad-double MGS (threshold 2^-200 ||A||_F) flags every solve singular."""
+    f = synth.system_from_terms(2, [[(1, {0: 2}), (-1, {})], [(1, {1: 2}), (-1, {})]])
+    g = synth.gamma_of(synth.tracking_small())
+    r = oracle.track_path(f, g, np.zeros((2, 2, 4)), oracle.Opts(prec=4))
+    assert oracle.REASONS[r["reason"]] == "SINGULAR" and r["status"] == -1
+
+
+# ---------------------------------------------------------------------------
+# Explicit start systems g (Eq. (1) allows any g with known roots)
+# ---------------------------------------------------------------------------
+def _diagonal_start(rng, deg):
+    """g_i = a_i x_i^{d_i} - b_i with random complex a_i, b_i: not the
+    total-degree start system, roots x_i = (b_i / a_i)^{1/d_i} omega^k in
+    closed form (computed here in mpmath, not by the oracle)."""
+    a = [synth.unit_complex(rng) * (0.5 + rng.uniform()) for _ in deg]
+    b = [synth.unit_complex(rng) * (0.5 + rng.uniform()) for _ in deg]
+    g = synth.system_from_terms(len(deg), [[(a[i], {i: int(d)}), (-b[i], {})] for i, d in enumerate(deg)])
+    return g, a, b
+
+
+def _diagonal_roots(a, b, deg, L, paths):
+    import mpmath
+    mpmath.mp.dps = 80
+    X = np.zeros((len(paths), len(deg), 2, L))
+    for q, p in enumerate(paths):
+        rem = int(p)
+        for i, d in enumerate(deg):
+            k = rem % int(d)
+            rem //= int(d)
+            z = mpmath.root(mpmath.mpc(b[i].real, b[i].imag) / mpmath.mpc(a[i].real, a[i].imag), int(d), k)
+            for c, part in enumerate((z.real, z.imag)):
+                r = part
+                for l in range(L):
+                    v = float(r)
+                    X[q, i, c, l] = v
+                    r -= mpmath.mpf(v)
+    return X
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_custom_start_f_equals_g_stays_put(L):
+    """f = g for a start system that is not x^d - 1: H = (gamma(1-t) + t) g, so
+    every path stays at its start point, which is a root of g only up to the
+    rounding of its limbs; the endpoint must be that root to ~u_L."""
+    rng = np.random.default_rng(31)
+    deg = [2, 3, 2]
+    g, a, b = _diagonal_start(rng, deg)
+    paths = np.arange(12)
+    X0 = _diagonal_roots(a, b, deg, L, paths)
+    r = oracle.track(g, complex(np.cos(0.4), np.sin(0.4)), paths, oracle.Opts(prec=L), start=g, x0=X0)
+    assert np.all(r["status"] == 1)
+    d = np.abs(limb_sum_diff(r["x"], X0)).max()
+    assert d <= 64 * U[L], d
+
+
+@pytest.mark.parametrize("L", [1, 2])
+def test_custom_start_reaches_the_same_endpoints(L):
+    """The endpoints of the n = 3, degree-2 workload do not depend on the start
+    system: tracked from a diagonal start system with random coefficients they
+    are, as a set, the endpoints tracked from x_i^2 - 1 (and each has a
+    residual at the rounding level)."""
+    s = synth.tracking_small()
+    gam = synth.gamma_of(s)
+    rng = np.random.default_rng(41)
+    deg = [2, 2, 2]
+    g, a, b = _diagonal_start(rng, deg)
+    X0 = _diagonal_roots(a, b, deg, L, np.arange(8))
+    custom = oracle.track(s, gam, np.arange(8), oracle.Opts(prec=L), start=g, x0=X0)
+    total = oracle.track(s, gam, range(8), oracle.Opts(prec=L))
+    assert np.all(custom["status"] == 1) and np.all(total["status"] == 1)
+    assert _residual_ok(s, custom, L)
+    Ec, Et = _cx(custom["x"]), _cx(total["x"])
+    for z in Ec:
+        assert np.min(np.abs(Et - z).max(-1)) <= 1e-10
+    for z in Et:
+        assert np.min(np.abs(Ec - z).max(-1)) <= 1e-10
+
+
+# ---------------------------------------------------------------------------
+# The residual half of the corrector's convergence test, and the endpoint check
+# ---------------------------------------------------------------------------
+def test_residual_test_binds():
+    """Section 2 ends the corrector when the residual AND the update are small.
+    With tol_res so small that no residual can meet it, no step converges and
+    every path ends by step-size underflow; with the default the same paths
+    all succeed; with tol_res = inf the update test alone decides and, on this
+    well-conditioned workload, gives the same endpoints."""
+    s = synth.tracking_small()
+    g = synth.gamma_of(s)
+    r = oracle.track(s, g, range(4), oracle.Opts(prec=1, tol_res=1e-300))
+    assert all(oracle.REASONS[int(v)] == "STEP_UNDERFLOW" for v in r["reason"])
+    a = oracle.track(s, g, range(8), oracle.Opts(prec=2))
+    b = oracle.track(s, g, range(8), oracle.Opts(prec=2, tol_res=float("inf")))
+    assert np.all(a["status"] == 1) and np.all(b["status"] == 1)
+    assert np.abs(limb_sum_diff(a["x"], b["x"])).max() <= 1e-28
+
+
+def test_polished_endpoint_beyond_diverge_norm_fails():
+    """A polished endpoint must lie within diverge_norm.  f = -(x - 2)(x - 4)
+    is concave on the real axis, so Newton from the start point x = 1 climbs
+    to the root 2 from below: with one step straight to t = 1 and a loose
+    corrector (tol_dx = 0.5, one Newton step) the point accepted at t = 1 is
+    x = 1.75, inside diverge_norm = 1.9; the polish then reaches x = 2, which
+    must end the path as DIVERGED rather than report success."""
+    f = synth.system_from_terms(1, [[(-1, {0: 2}), (6, {0: 1}), (-8, {})]])
+    gamma = complex(np.cos(0.3), np.sin(0.3))
+    loose = dict(prec=1, tol_dx=0.5, tol_res=float("inf"), h_init=1.0, h_max=1.0, max_newton=1)
+    x0 = oracle.start_solution(1, np.array([2], dtype=np.int32), 0)      # x = 1
+    assert _cx(x0)[0] == 1.0
+    r1 = oracle.track_path(f, gamma, x0, oracle.Opts(**loose))
+    assert r1["status"] == 1 and r1["steps"] == 1 and abs(_cx(r1["x"])[0] - 2.0) <= 1e-14
+    r2 = oracle.track_path(f, gamma, x0, oracle.Opts(**loose, diverge_norm=1.9))
+    assert r2["status"] == -1 and oracle.REASONS[r2["reason"]] == "DIVERGED"
