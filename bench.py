@@ -301,6 +301,7 @@ def unfused_extra(ph, torch, S, sysm, gamma, steps):
     terms = sysm.n_terms + 2 * sysm.n_eq
     for L in (1, 2):
         ph.eval_set_config(S, L, ph.EVAL_UNFUSED)
+        ph.eval_prepare(S, L, unfused_points=npts)
         ms, ok, _, _ = time_eval(ph, torch, S, sysm, L, npts, steps, 1, gamma)
         ph.eval_set_config(S, L)
         fused, _, _, _ = time_eval(ph, torch, S, sysm, L, npts, steps, 1, gamma)
@@ -467,6 +468,8 @@ def main():
     x0, t0 = synth.torus_points(sysm, npts, L)
     if args.kernel:
         ph.eval_set_config(S, L, args.kernel)
+        if args.kernel == ph.EVAL_UNFUSED:
+            ph.eval_prepare(S, L, unfused_points=npts)
     elif not args.no_autotune:
         # the library's autotuner picks kernel and tiling on this workload; a
         # choice already in the PH_AUTOTUNE_CACHE file is taken as it is

@@ -111,13 +111,34 @@ int ph_start_solutions(const ph_system *target, int32_t prec, int64_t first_path
  *   x      : device SoA, rows (var*2+c)*prec+l, leading dimension ld
  *   val    : device SoA output, rows (eq*2+c)*prec+l
  *   jac    : device SoA output, rows ((eq*n_var+var)*2+c)*prec+l, or NULL
- * npts = 0 is a no-op.  No allocation; asynchronous on stream.  NaN/Inf
- * inputs propagate unchecked.  Errors: PH_EINVAL (null pointers, ld < npts,
- * start shape differs from target), PH_EHIP (launch failure).
+ * npts = 0 is a no-op.  No allocation and no synchronisation: the call only
+ * queues kernels on stream (it may be captured in a hipGraph).  The term
+ * tables of (target, NULL) exist from ph_system_create; those of (target,
+ * start) are built once by ph_eval_prepare, and a start system that was not
+ * prepared for this target is PH_EINVAL.  A tuned configuration is looked up
+ * in memory (the handle, or the PH_AUTOTUNE_CACHE entries read when target was
+ * created).  NaN/Inf inputs propagate unchecked.  Errors: PH_EINVAL (null
+ * pointers, ld < npts, start shape differs from target, start not prepared,
+ * unfused design without prepared arrays), PH_EHIP (launch failure).
  */
 int ph_eval_jac(const ph_system *target, const ph_system *start, const double gamma[2],
                 int32_t prec, int64_t npts, const double *t, const double *x, int64_t ld,
                 double *val, double *jac, void *stream);
+
+/*
+ * ph_eval_prepare -- the one point where ph_eval_jac's device data for
+ * (target, start) is allocated: builds the merged term table of f and the
+ * start system g of Eq. (1) (start NULL: the total-degree table, which
+ * ph_system_create already built), and, with unfused_points > 0, sizes the
+ * intermediate arrays of the unfused design (kernel 5 of ph_eval_set_config:
+ * (terms + slots) * 16 * prec bytes per point) for that many points of
+ * precision prec; larger batches then run in chunks of that many points.
+ * Idempotent and grow-only.  Allocates device memory and synchronises the
+ * device.  Errors: PH_EINVAL (null target, bad prec, unfused_points < 0,
+ * start shape differs from target), PH_ENOMEM, PH_EHIP.
+ */
+int ph_eval_prepare(ph_system *target, const ph_system *start, int32_t prec,
+                    int64_t unfused_points);
 
 /*
  * ph_eval_set_config -- pin the kernel and tiling ph_eval_jac uses for
@@ -127,9 +148,10 @@ int ph_eval_jac(const ph_system *target, const ph_system *start, const double ga
  * with the row in pinned registers, 4 the same with a compiler-held row,
  * 5 the paper's unfused design (coeff, mon and sum kernels with the
  * coefficients and the k + 1 products of every term and point stored in
- * device memory between them; an ablation of the fused kernels, caching its
- * intermediate arrays -- (terms + slots) * 16 * prec bytes per point -- in
- * the system handle; waves and groups are ignored);
+ * device memory between them; an ablation of the fused kernels, whose
+ * intermediate arrays ph_eval_prepare sizes; waves and groups are ignored);
+ * kernels 2, 3 and 4 produce the Jacobian: a values-only call (jac NULL)
+ * runs the general kernel with the same waves and groups;
  * waves = waves per workgroup sharing one 64-point tile (1..8, 0 default;
  * taken as given, so counts like 6 can match the register budget);
  * groups = equation groups per tile (power of two, 0 default).  All zero
@@ -142,8 +164,9 @@ int ph_eval_set_config(ph_system *target, const ph_system *start, int32_t prec, 
 /*
  * ph_eval_get_config -- the configuration ph_eval_jac would use for (target,
  * start, prec): the one pinned or tuned in this handle, else the last entry
- * for these systems in the PH_AUTOTUNE_CACHE file (which the handle then
- * keeps); all zero: automatic.  Host-only; PH_EINVAL on null pointers.
+ * for these systems in the PH_AUTOTUNE_CACHE file as read when target was
+ * created (which the handle then keeps); all zero: automatic.  Host-only;
+ * PH_EINVAL on null pointers.
  */
 int ph_eval_get_config(const ph_system *target, const ph_system *start, int32_t prec,
                        int32_t *kernel, int32_t *waves, int32_t *groups);
@@ -179,8 +202,13 @@ int ph_eval_autotune(ph_system *target, const ph_system *start, const double gam
  *   polish_max      Newton steps of the polish at t = 1 (8)
  *   h_init, h_min, h_max   initial / smallest / largest step (0.01, 1e-10, 0.1)
  *   shrink, expand  step factors after rejection / expansion (0.5, 1.5)
- *   tol_dx          corrector converged when ||dx|| <= tol_dx max(1,||x||) (1e-8)
- *   diverge_norm    ||x||_inf beyond this fails the path (1e8)
+ *   tol_dx, tol_res corrector converged when ||dx||_inf <= tol_dx max(1,||x||_inf)
+ *                   and the residual at the point where the Newton system
+ *                   was formed satisfies ||H||_inf <= tol_res ||J||_F
+ *                   max(1,||x||_inf) (Section 2: residuals and updates small;
+ *                   norms in FP64 from the leading limbs; 1e-8, 1e-6)
+ *   diverge_norm    ||x||_inf beyond this fails the path, also after the
+ *                   polish (1e8)
  *   polish_tol      polish target relative to max(1,||x||); < 0 selects 8 u_prec
  *   max_steps       predictor steps per path (100000)
  *   schedule        PH_SCHED_PERSISTENT (one persistent kernel drains a device
@@ -203,6 +231,7 @@ typedef struct {
     int64_t max_steps;
     int32_t schedule, rounds_per_launch, launches_per_sync, blocks_per_cu;
     int32_t lanes_per_path;
+    double tol_res;
 } ph_track_opts;
 
 /* Counts filled by ph_track when a report pointer is given. */

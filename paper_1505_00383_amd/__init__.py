@@ -25,7 +25,7 @@ REASONS = {0: "NONE", 1: "SUCCESS", 2: "DIVERGED", 3: "STEP_UNDERFLOW", 4: "MAX_
 EXPORTED = ["ph_system_create", "ph_system_destroy", "ph_system_info", "ph_system_degrees",
             "ph_start_solutions", "ph_eval_jac", "ph_track_opts_default", "ph_last_error",
             "ph_arith_probe", "ph_track", "ph_track_batch", "ph_eval_set_config",
-            "ph_eval_autotune", "ph_track_autotune", "ph_eval_get_config"]
+            "ph_eval_autotune", "ph_track_autotune", "ph_eval_get_config", "ph_eval_prepare"]
 
 # ph_eval_set_config kernels
 EVAL_AUTO, EVAL_GENERAL, EVAL_REGROW, EVAL_FAST, EVAL_FAST_VECROW, EVAL_UNFUSED = 0, 1, 2, 3, 4, 5
@@ -42,7 +42,8 @@ class TrackOpts(ctypes.Structure):
                 ("diverge_norm", ctypes.c_double), ("polish_tol", ctypes.c_double),
                 ("max_steps", ctypes.c_int64), ("schedule", ctypes.c_int32),
                 ("rounds_per_launch", ctypes.c_int32), ("launches_per_sync", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("lanes_per_path", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("lanes_per_path", ctypes.c_int32),
+                ("tol_res", ctypes.c_double)]
 
 
 SCHED_PERSISTENT, SCHED_GRAPH = 0, 1
@@ -98,6 +99,7 @@ def load_library(path: str = LIB_PATH):
     L.ph_track.argtypes = [P, P, P, i64, P, i64, P, P, P, P, P, P, P]
     L.ph_track_batch.argtypes = [i32, P, P, P, P, P, P, i64, P, P, P, P, P]
     L.ph_eval_set_config.argtypes = [P, P, i32, i32, i32, i32]
+    L.ph_eval_prepare.argtypes = [P, P, i32, i64]
     L.ph_eval_get_config.argtypes = [P, P, i32, P, P, P]
     L.ph_eval_autotune.argtypes = [P, P, P, i32, i64, P, P, i64, P, P, P, P]
     L.ph_track_autotune.argtypes = [i32, P, P, P, P, P, i64, P, P, P]
@@ -223,6 +225,15 @@ def eval_jac(sys: System, x_soa, npts: int, prec: int, t=None, gamma=1.0 + 0j, s
                             _ptr(t), _ptr(x_soa), ld, _ptr(val), _ptr(jac) if want_jac else None,
                             _stream(stream)))
     return val, (jac if want_jac else None)
+
+
+def eval_prepare(sys: System, prec: int = 1, start: System | None = None,
+                 unfused_points: int = 0):
+    """Build the term tables of (sys, start) and, with unfused_points > 0, size the
+    unfused design's arrays for that many points of prec limbs (ph_eval_prepare).
+    ph_eval_jac itself never allocates: a start system must be prepared first."""
+    _check(load_library().ph_eval_prepare(sys.handle, None if start is None else start.handle,
+                                          prec, unfused_points))
 
 
 def eval_set_config(sys: System, prec: int, kernel: int = EVAL_AUTO, waves: int = 0,

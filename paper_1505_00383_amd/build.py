@@ -28,15 +28,33 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
           "-munsafe-fp-atomics"]
 
 
+# track_unit.hip holds the tracker launchers for one (residual limbs, FP64
+# solves) pair per compilation: six objects built in parallel.
+TRACK_UNIT = "track_unit.hip"
+TRACK_VARIANTS = [(L, m) for L in (1, 2, 4) for m in (1, 0)]
+
+
 def sources():
-    return sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
+    """(source, object name, extra flags) of every compilation."""
+    out = []
+    # the heaviest compilations first: the tracker units, then eval.hip
+    for f in sorted(os.listdir(CSRC), key=lambda f: (f != TRACK_UNIT, f != "eval.hip", f)):
+        if not f.endswith((".hip", ".cpp")):
+            continue
+        if f == TRACK_UNIT:
+            for L, m in TRACK_VARIANTS:
+                out.append((f, f"track_l{L}{'m' if m else 'p'}.o",
+                            [f"-DPH_TRACK_L={L}", f"-DPH_TRACK_MIXED={m}"]))
+        else:
+            out.append((f, f + ".o", []))
+    return out
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, src + ".o")
-    cmd = [HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, src), "-o", obj]
-    if src.endswith(".hip"):
-        cmd = [HIPCC, "-x", "hip"] + COMMON + DEVICE + ["-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(job) -> str:
+    src, oname, extra = job
+    obj = os.path.join(BUILD, oname)
+    lang = ["-x", "hip"] if src.endswith(".hip") else []
+    cmd = [HIPCC] + lang + COMMON + DEVICE + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")

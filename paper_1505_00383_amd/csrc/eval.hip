@@ -338,6 +338,10 @@ struct VecRow {
 // clobbered (which also makes the kernel descriptor reserve 256 registers).
 // A partial is added with the column index applied by the GPR indexing mode
 // to the destination and addend of two FP64 FMAs: no register moves at all.
+// s_set_gpr_idx_on writes the index into M0.  The compiler reserves M0 and
+// does not honour it in a clobber list, so instead the compiled pinned
+// kernels are checked to contain no compiler-generated instruction that uses
+// M0 at all (no value of the compiler's can live in M0 across these blocks).
 // fma takes twice the column index; callers guarantee 0 <= j < 32 (the fast
 // path requires n_var <= 32).
 #define PH_PIN_CLOBBERS "v128","v129","v130","v131","v132","v133","v134","v135","v136","v137","v138","v139","v140","v141","v142","v143","v144","v145","v146","v147","v148","v149","v150","v151","v152","v153","v154","v155","v156","v157","v158","v159","v160","v161","v162","v163","v164","v165","v166","v167","v168","v169","v170","v171","v172","v173","v174","v175","v176","v177","v178","v179","v180","v181","v182","v183","v184","v185","v186","v187","v188","v189","v190","v191","v192","v193","v194","v195","v196","v197","v198","v199","v200","v201","v202","v203","v204","v205","v206","v207","v208","v209","v210","v211","v212","v213","v214","v215","v216","v217","v218","v219","v220","v221","v222","v223","v224","v225","v226","v227","v228","v229","v230","v231","v232","v233","v234","v235","v236","v237","v238","v239","v240","v241","v242","v243","v244","v245","v246","v247","v248","v249","v250","v251","v252","v253","v254","v255"
@@ -673,6 +677,9 @@ int eval_launch(const DevTable &tab, const double gamma[2], int prec, int64_t np
     const bool can_reg = prec == 1 && wj && tab.n_var <= 32 && tab.kmax <= 16;
     int kernel = cfg ? cfg->kernel : 0;
     if (kernel == 5) return unfused_launch(tab, gamma, prec, npts, t, x, ld, val, jac, st);
+    // the register-row kernels produce the Jacobian; values alone take the
+    // general kernel with the same tiling
+    if (!wj && kernel >= 2) kernel = 1;
     if ((kernel == 3 || kernel == 4) && !can_fast)
         return fail(PH_EUNSUPPORTED, "fast path not available for this system");
     if (kernel == 2 && !can_reg) return fail(PH_EUNSUPPORTED, "register-row kernel not available");
@@ -752,8 +759,9 @@ static int eval_check(const ph_system *target, const ph_system *start, const dou
     return PH_OK;
 }
 
-// Look up a tuned configuration: in the handle, else in the PH_AUTOTUNE_CACHE
-// file (lines "eval <target fp> <start fp> <prec> <kernel> <W> <G> <ms>").
+// Look up a tuned configuration: in the handle, else among the entries of
+// the PH_AUTOTUNE_CACHE file read when the target was created (memory only:
+// an evaluation never touches the file system).
 static bool eval_cfg_lookup(const ph_system *target, const ph_system *start, int prec, EvalCfg &out)
 {
     ph_system *tg = const_cast<ph_system *>(target);
@@ -763,27 +771,11 @@ static bool eval_cfg_lookup(const ph_system *target, const ph_system *start, int
         out = it->second;
         return true;
     }
-    const char *path = std::getenv("PH_AUTOTUNE_CACHE");
-    if (!path) return false;
-    FILE *f = std::fopen(path, "r");
-    if (!f) return false;
-    const unsigned long long sfp = start ? start->h.fingerprint : 0ull;
-    unsigned long long a = 0, b = 0;
-    int p = 0, k = 0, w = 0, g = 0;
-    double ms = 0;
-    bool found = false;
-    char tag[16];
-    while (std::fscanf(f, "%15s %llx %llx %d %d %d %d %lf", tag, &a, &b, &p, &k, &w, &g, &ms) == 8) {
-        if (std::strcmp(tag, "eval") == 0 && a == target->h.fingerprint && b == sfp && p == prec) {
-            out.kernel = k;
-            out.W = w;
-            out.G = g;
-            found = true;  // the last entry wins
-        }
-    }
-    std::fclose(f);
-    if (found) tg->eval_cfg[{start, prec}] = out;
-    return found;
+    auto ft = tg->file_cfg.find({start ? start->h.fingerprint : 0ull, prec});
+    if (ft == tg->file_cfg.end()) return false;
+    out = ft->second;
+    tg->eval_cfg[{start, prec}] = out;
+    return true;
 }
 
 }  // namespace ph
@@ -797,12 +789,28 @@ extern "C" int ph_eval_jac(const ph_system *target, const ph_system *start, cons
     int rc = eval_check(target, start, gamma, prec, npts, t, x, ld, val);
     if (rc || npts == 0) return rc;
     const DevTable *tab = nullptr;
-    rc = get_table(target, start, &tab);
+    rc = find_table(target, start, &tab);  // built by ph_system_create / ph_eval_prepare
     if (rc) return rc;
     EvalCfg cfg;
     const bool tuned = eval_cfg_lookup(target, start, prec, cfg);
     return eval_launch(*tab, gamma, prec, npts, t, x, ld, val, jac, (hipStream_t)stream,
                        tuned ? &cfg : nullptr);
+}
+
+extern "C" int ph_eval_prepare(ph_system *target, const ph_system *start, int32_t prec,
+                               int64_t unfused_points)
+{
+    if (!target) return fail(PH_EINVAL, "null target system");
+    if (prec != 1 && prec != 2 && prec != 4) return fail(PH_EINVAL, "prec must be 1, 2 or 4");
+    if (unfused_points < 0) return fail(PH_EINVAL, "unfused_points < 0");
+    if (start && (start->h.n_eq != target->h.n_eq || start->h.n_var != target->h.n_var))
+        return fail(PH_EINVAL, "start system shape differs from target");
+    const DevTable *tab = nullptr;
+    int rc = get_table(target, start, &tab);
+    if (rc) return rc;
+    if (unfused_points > 0)
+        rc = prepare_unfused(target, const_cast<DevTable &>(*tab), prec, unfused_points);
+    return rc;
 }
 
 extern "C" int ph_eval_set_config(ph_system *target, const ph_system *start, int32_t prec,

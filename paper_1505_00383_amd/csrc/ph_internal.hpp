@@ -83,8 +83,8 @@ struct DevTable {
     int32_t *u_off = nullptr;    // [n_eq * (1 + n_var) + 1] slots summed into each output
     int32_t *u_list = nullptr;   //   entry: H_i (entries 0..n_eq-1), then J_ij row-major
     void *block = nullptr;       // single device allocation holding all of the above
-    void *u_scratch = nullptr;   // grow-only intermediate arrays of the unfused design
-    size_t u_scratch_bytes = 0;
+    void *u_scratch = nullptr;   // grow-only intermediate arrays of the unfused design,
+    size_t u_scratch_bytes = 0;  //   sized by ph_eval_prepare (never by an evaluation)
 };
 
 // Kernel choice and tiling of one evaluation: kernel 0 automatic, 1 general
@@ -113,6 +113,9 @@ struct ph_system {
     std::mutex mu;
     std::map<const ph_system *, ph::DevTable> with_start;  // custom start systems
     std::map<std::pair<const ph_system *, int>, ph::EvalCfg> eval_cfg;  // (start, prec) -> config
+    // entries of the PH_AUTOTUNE_CACHE file for this target, read once when
+    // the handle is created: (start fingerprint or 0, prec) -> config
+    std::map<std::pair<uint64_t, int>, ph::EvalCfg> file_cfg;
     int device = 0;
 };
 
@@ -121,8 +124,16 @@ namespace ph {
 // total-degree start system g_i = x_i^{d_i} - 1.
 int build_table(const HostSystem &f, const HostSystem *g, DevTable &out);
 void free_table(DevTable &t);
-// Table for (target, start), built on first use and cached in the target.
+// Table for (target, start), built on first use and cached in the target
+// (allocates and synchronises when it builds).
 int get_table(const ph_system *target, const ph_system *start, const DevTable **out);
+// The same without building: PH_EINVAL when (target, start) was not prepared.
+int find_table(const ph_system *target, const ph_system *start, const DevTable **out);
+// Size the unfused design's intermediate arrays for npts points of prec limbs
+// (grow-only; synchronises the device before releasing a smaller buffer).
+int prepare_unfused(const ph_system *target, DevTable &tab, int prec, int64_t npts);
+// Entries of the PH_AUTOTUNE_CACHE file for this target (called at creation).
+void load_eval_cache(ph_system *s);
 // The unfused three-kernel evaluation (kernel choice 5).
 int unfused_launch(const DevTable &tab, const double gamma[2], int prec, int64_t npts,
                    const double *t, const double *x, int64_t ld, double *val, double *jac,

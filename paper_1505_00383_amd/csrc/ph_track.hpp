@@ -60,6 +60,14 @@ struct TrackArgs {
 };
 
 int track_launch(const TrackArgs &a, int prec, int kmax, int blocks, size_t lds, hipStream_t st);
+// Per (residual limbs L, FP64 solves) launchers and slot-state helpers,
+// instantiated in track_unit.hip.
+template <int L, bool MIXED>
+int track_launch_t(const TrackArgs &a, int kmax, int blocks, size_t lds, hipStream_t st);
+template <int L>
+size_t slot_bytes_t();
+template <int L>
+int slot_init_launch_t(void *state, int64_t nslots, hipStream_t st);
 size_t track_lds_bytes(int prec, int mixed, int np_max);
 size_t slot_bytes(int prec);
 int slot_init_launch(int prec, void *state, int64_t nslots, hipStream_t st);

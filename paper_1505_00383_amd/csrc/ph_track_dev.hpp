@@ -428,6 +428,9 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
         }
 
         // ---- correct: MGS least squares on [J | -H], row i in lane i ------
+        // residual at the point where the Newton system is formed (the
+        // convergence test compares it with ||J||_F, Section 2)
+        const double hres = gmax_d<NP>((busy && i < n) ? c_absd<LS>(lds_get<LS>(W(NP, i))) : 0.0);
         double fro = 0.0;
 #pragma unroll
         for (int j = 0; j < NP; ++j) {
@@ -500,9 +503,10 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
                 xh = widen_add<L, LS>(xh, dxi);
                 const double dn = gmax_d<NP>(i < n ? c_absd<LS>(dxi) : 0.0);
                 const double xn = gmax_d<NP>(i < n ? c_absd<L>(xh) : 0.0);
+                const double sx = xn > 1.0 ? xn : 1.0;
                 if (dn != dn || xn != xn) {
                     reject = true;
-                } else if (dn <= o.tol_dx * (xn > 1.0 ? xn : 1.0)) {
+                } else if (dn <= o.tol_dx * sx && hres <= o.tol_res * fro * sx) {
                     accept = true;
                 } else if (it >= 1 && dn > dprev) {
                     reject = true;
@@ -553,13 +557,14 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
             }
         } else if (phase == PH_POLISH) {
             // Newton on f at t = 1 until the update meets polish_tol, stops
-            // halving, or polish_max steps were taken
+            // halving, or polish_max steps were taken; an update that is not
+            // finite ends the polish without being applied
             bool done = false;
             if (sing) {
                 done = true;
             } else {
                 const double dn = gmax_d<NP>(i < n ? c_absd<LS>(dxi) : 0.0);
-                if (pit > 0 && !(dn < 0.5 * dprev)) {
+                if (!isfinite(dn) || (pit > 0 && !(dn < 0.5 * dprev))) {
                     done = true;
                 } else {
                     x = widen_add<L, LS>(x, dxi);
@@ -572,7 +577,12 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
                 }
             }
             xh = x;
-            if (done) finish(PH_R_SUCCESS);
+            if (done) {
+                // the endpoint must be finite and within diverge_norm
+                const bool bad = gmax_d<NP>((i < n && c_bad<L>(x)) ? 1.0 : 0.0) > 0.0;
+                const double xe = gmax_d<NP>(i < n ? c_absd<L>(x) : 0.0);
+                finish(bad ? PH_R_NAN : (xe > o.diverge_norm ? PH_R_DIVERGED : PH_R_SUCCESS));
+            }
         }
     }
     S.phase = phase;

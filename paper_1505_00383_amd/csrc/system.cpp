@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -306,6 +308,63 @@ int get_table(const ph_system *target, const ph_system *start, const DevTable **
     return PH_OK;
 }
 
+int find_table(const ph_system *target, const ph_system *start, const DevTable **out)
+{
+    if (!start) {
+        *out = &target->total;
+        return PH_OK;
+    }
+    ph_system *t = const_cast<ph_system *>(target);
+    std::lock_guard<std::mutex> lk(t->mu);
+    auto it = t->with_start.find(start);
+    if (it == t->with_start.end())
+        return fail(PH_EINVAL, "start system not prepared for this target: call ph_eval_prepare first");
+    *out = &it->second;
+    return PH_OK;
+}
+
+int prepare_unfused(const ph_system *target, DevTable &tab, int prec, int64_t npts)
+{
+    const int64_t lu = (npts + 63) / 64 * 64;
+    const size_t need = (size_t)(tab.n_terms + tab.u_slots) * 2 * prec * lu * sizeof(double);
+    std::lock_guard<std::mutex> lk(const_cast<ph_system *>(target)->mu);
+    if (tab.u_scratch_bytes >= need) return PH_OK;
+    if (tab.u_scratch) {
+        // the previous buffer may still be read by work queued on any stream
+        PH_HIP(hipDeviceSynchronize());
+        (void)hipFree(tab.u_scratch);
+        tab.u_scratch = nullptr;
+        tab.u_scratch_bytes = 0;
+    }
+    if (hipMalloc(&tab.u_scratch, need) != hipSuccess) {
+        tab.u_scratch = nullptr;
+        return fail(PH_ENOMEM, "unfused evaluation: intermediate arrays do not fit");
+    }
+    tab.u_scratch_bytes = need;
+    return PH_OK;
+}
+
+void load_eval_cache(ph_system *s)
+{
+    const char *path = std::getenv("PH_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        char tag[16];
+        unsigned long long a = 0, b = 0;
+        int p = 0, k = 0, w = 0, g = 0;
+        double ms = 0;
+        // lines "eval <target fp> <start fp> <prec> <kernel> <W> <G> <ms>";
+        // other tags (the tracker's) have their own layout
+        if (std::sscanf(line, "%15s %llx %llx %d %d %d %d %lf", tag, &a, &b, &p, &k, &w, &g, &ms) == 8 &&
+            std::strcmp(tag, "eval") == 0 && a == s->h.fingerprint)
+            s->file_cfg[{(uint64_t)b, p}] = EvalCfg{k, w, g};  // the last entry wins
+    }
+    std::fclose(f);
+}
+
 static int validate(int32_t n_eq, int32_t n_var, const int32_t *eq_term_off,
                     const int32_t *term_fac_off, const int32_t *fac_var, const int32_t *fac_exp,
                     const double *coef, int32_t coef_limbs)
@@ -399,6 +458,7 @@ extern "C" int ph_system_create(int32_t n_eq, int32_t n_var, const int32_t *eq_t
     PH_HIP(hipGetDevice(&s->device));
     rc = build_table(h, nullptr, s->total);
     if (rc) return rc;
+    load_eval_cache(s.get());
     *out = s.release();
     return PH_OK;
 }
@@ -456,5 +516,6 @@ extern "C" int ph_track_opts_default(ph_track_opts *o)
     o->launches_per_sync = 8;
     o->blocks_per_cu = 0;
     o->lanes_per_path = 0;
+    o->tol_res = 1e-6;
     return PH_OK;
 }

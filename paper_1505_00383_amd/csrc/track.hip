@@ -1,7 +1,7 @@
 // track.hip -- many-path tracking of gamma (1-t) g(x) + t f(x) = 0 from t = 0 to
 // t = 1 (Section 2 of the paper, Tables 1-3), on one GPU: host side.  The
-// device code (ph_track_dev.hpp) is compiled per residual precision in
-// track_l1.hip, track_l2.hip and track_l4.hip.
+// device code (ph_track_dev.hpp) is compiled per residual precision and solve
+// precision from track_unit.hip.
 #include <hip/hip_runtime.h>
 
 #include "ph_internal.hpp"
@@ -9,34 +9,21 @@
 
 namespace ph {
 
-int track_launch_l1m(const TrackArgs &a, int kmax, int blocks, size_t lds, hipStream_t st);
-int track_launch_l2m(const TrackArgs &a, int kmax, int blocks, size_t lds, hipStream_t st);
-int track_launch_l4m(const TrackArgs &a, int kmax, int blocks, size_t lds, hipStream_t st);
-int track_launch_l1p(const TrackArgs &a, int kmax, int blocks, size_t lds, hipStream_t st);
-int track_launch_l2p(const TrackArgs &a, int kmax, int blocks, size_t lds, hipStream_t st);
-int track_launch_l4p(const TrackArgs &a, int kmax, int blocks, size_t lds, hipStream_t st);
-size_t slot_bytes_l1();
-size_t slot_bytes_l2();
-size_t slot_bytes_l4();
-int slot_init_launch_l1(void *state, int64_t nslots, hipStream_t st);
-int slot_init_launch_l2(void *state, int64_t nslots, hipStream_t st);
-int slot_init_launch_l4(void *state, int64_t nslots, hipStream_t st);
-
 __global__ void clear_counter_kernel(unsigned int *c) { *c = 0u; }
 
 int track_launch(const TrackArgs &a, int prec, int kmax, int blocks, size_t lds, hipStream_t st)
 {
     if (a.o.mixed) {
         switch (prec) {
-        case 1: return track_launch_l1m(a, kmax, blocks, lds, st);
-        case 2: return track_launch_l2m(a, kmax, blocks, lds, st);
-        default: return track_launch_l4m(a, kmax, blocks, lds, st);
+        case 1: return track_launch_t<1, true>(a, kmax, blocks, lds, st);
+        case 2: return track_launch_t<2, true>(a, kmax, blocks, lds, st);
+        default: return track_launch_t<4, true>(a, kmax, blocks, lds, st);
         }
     }
     switch (prec) {
-    case 1: return track_launch_l1p(a, kmax, blocks, lds, st);
-    case 2: return track_launch_l2p(a, kmax, blocks, lds, st);
-    default: return track_launch_l4p(a, kmax, blocks, lds, st);
+    case 1: return track_launch_t<1, false>(a, kmax, blocks, lds, st);
+    case 2: return track_launch_t<2, false>(a, kmax, blocks, lds, st);
+    default: return track_launch_t<4, false>(a, kmax, blocks, lds, st);
     }
 }
 
@@ -49,13 +36,13 @@ size_t track_lds_bytes(int prec, int mixed, int np_max)
 
 size_t slot_bytes(int prec)
 {
-    return prec == 1 ? slot_bytes_l1() : (prec == 2 ? slot_bytes_l2() : slot_bytes_l4());
+    return prec == 1 ? slot_bytes_t<1>() : (prec == 2 ? slot_bytes_t<2>() : slot_bytes_t<4>());
 }
 
 int slot_init_launch(int prec, void *state, int64_t nslots, hipStream_t st)
 {
-    return prec == 1 ? slot_init_launch_l1(state, nslots, st)
-                     : (prec == 2 ? slot_init_launch_l2(state, nslots, st) : slot_init_launch_l4(state, nslots, st));
+    return prec == 1 ? slot_init_launch_t<1>(state, nslots, st)
+                     : (prec == 2 ? slot_init_launch_t<2>(state, nslots, st) : slot_init_launch_t<4>(state, nslots, st));
 }
 
 int clear_counter_launch(unsigned int *c, hipStream_t st)
@@ -89,7 +76,7 @@ static int check_opts(const ph_track_opts &o)
     if (o.max_newton < 1 || o.expand_after < 1 || o.polish_max < 0 || o.max_steps < 0)
         return fail(PH_EINVAL, "invalid iteration counts in opts");
     if (!(o.h_init > 0) || !(o.h_max > 0) || !(o.h_min >= 0) || !(o.shrink > 0 && o.shrink < 1) ||
-        !(o.expand >= 1) || !(o.tol_dx > 0) || !(o.diverge_norm > 0))
+        !(o.expand >= 1) || !(o.tol_dx > 0) || !(o.diverge_norm > 0) || !(o.tol_res >= 0))
         return fail(PH_EINVAL, "invalid step-control constants in opts");
     if (o.lanes_per_path != 0 && o.lanes_per_path != 4 && o.lanes_per_path != 8 &&
         o.lanes_per_path != 16 && o.lanes_per_path != 32)
@@ -435,14 +422,16 @@ extern "C" int ph_track_autotune(int32_t nsys, const ph_system *const *targets, 
     const char *cache = std::getenv("PH_AUTOTUNE_CACHE");
     if (cache) {
         if (FILE *f = std::fopen(cache, "r")) {
-            char tag[16];
+            char line[512], tag[16];
             unsigned long long k = 0;
             int sch = 0, rnd = 0, bpc = 0, lanes = 0;
             double sec = 0;
             bool found = false;
             ph_track_opts o = *opts;
-            while (std::fscanf(f, "%15s %llx %d %d %d %d %lf", tag, &k, &sch, &rnd, &bpc, &lanes, &sec) == 7) {
-                if (std::strcmp(tag, "track") == 0 && k == key) {
+            // one entry per line; lines of other tags (the evaluation's) are skipped
+            while (std::fgets(line, sizeof line, f)) {
+                if (std::sscanf(line, "%15s %llx %d %d %d %d %lf", tag, &k, &sch, &rnd, &bpc, &lanes, &sec) == 7 &&
+                    std::strcmp(tag, "track") == 0 && k == key) {
                     o.schedule = sch;
                     o.rounds_per_launch = rnd;
                     o.blocks_per_cu = bpc;

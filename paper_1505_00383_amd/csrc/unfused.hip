@@ -11,7 +11,8 @@
 //
 // Every array is structure-of-arrays with the point index fastest, as in the
 // rest of the library.  The intermediate arrays (coefficients and slots)
-// live in a grow-only buffer cached in the term table.
+// live in a buffer of the term table that ph_eval_prepare sizes; points
+// beyond its capacity run in several chunks.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -152,8 +153,6 @@ __global__ void __launch_bounds__(256) sum_kernel(UArgs a)
     }
 }
 
-static std::mutex g_scratch_mu;
-
 template <int L>
 static int unfused_run(const DevTable &tab, const UArgs &a0, hipStream_t st)
 {
@@ -185,30 +184,13 @@ int unfused_launch(const DevTable &tab, const double gamma[2], int prec, int64_t
 {
     if ((size_t)tab.n_var * 2 * prec * 64 * sizeof(double) > 160 * 1024)
         return fail(PH_EUNSUPPORTED, "unfused evaluation stages the points in LDS (n * prec <= 160)");
-    const int64_t lu = (npts + 63) / 64 * 64;
-    const size_t need = (size_t)(tab.n_terms + tab.u_slots) * 2 * prec * lu * sizeof(double);
+    // the intermediate arrays were sized by ph_eval_prepare: the points run in
+    // chunks of the capacity they hold at this precision
+    const size_t per_point = (size_t)(tab.n_terms + tab.u_slots) * 2 * prec * sizeof(double);
+    const int64_t cap = tab.u_scratch ? (int64_t)(tab.u_scratch_bytes / per_point) / 64 * 64 : 0;
+    if (cap < 64)
+        return fail(PH_EINVAL, "unfused evaluation: size its arrays with ph_eval_prepare (unfused_points > 0)");
     UArgs a;
-    {
-        std::lock_guard<std::mutex> lk(g_scratch_mu);
-        DevTable &mt = const_cast<DevTable &>(tab);
-        if (mt.u_scratch_bytes < need) {
-            // the previous buffer may still be read by work queued earlier
-            // on any stream: wait before releasing it
-            if (mt.u_scratch) {
-                PH_HIP(hipDeviceSynchronize());
-                (void)hipFree(mt.u_scratch);
-                mt.u_scratch = nullptr;
-                mt.u_scratch_bytes = 0;
-            }
-            if (hipMalloc(&mt.u_scratch, need) != hipSuccess) {
-                mt.u_scratch = nullptr;
-                return fail(PH_ENOMEM, "unfused evaluation: intermediate arrays do not fit");
-            }
-            mt.u_scratch_bytes = need;
-        }
-        a.cff = static_cast<double *>(mt.u_scratch);
-    }
-    a.mon = a.cff + (size_t)tab.n_terms * 2 * prec * lu;
     a.eq_off = tab.eq_off;
     a.tdesc = tab.tdesc;
     a.fac = tab.fac;
@@ -216,24 +198,32 @@ int unfused_launch(const DevTable &tab, const double gamma[2], int prec, int64_t
     a.u_slot = tab.u_slot;
     a.u_off = tab.u_off;
     a.u_list = tab.u_list;
-    a.t = t;
-    a.x = x;
-    a.val = val;
-    a.jac = jac;
-    a.npts = npts;
     a.ld = ld;
-    a.lu = lu;
     a.n_terms = tab.n_terms;
     a.n_entries = (int64_t)tab.n_eq * (1 + tab.n_var);
     a.gre = gamma ? gamma[0] : 1.0;
     a.gim = gamma ? gamma[1] : 0.0;
     a.n_eq = tab.n_eq;
     a.n_var = tab.n_var;
-    switch (prec) {
-    case 1: return unfused_run<1>(tab, a, st);
-    case 2: return unfused_run<2>(tab, a, st);
-    default: return unfused_run<4>(tab, a, st);
+    for (int64_t p0 = 0; p0 < npts; p0 += cap) {
+        const int64_t m = npts - p0 < cap ? npts - p0 : cap;
+        a.npts = m;
+        a.lu = (m + 63) / 64 * 64;
+        a.cff = static_cast<double *>(tab.u_scratch);
+        a.mon = a.cff + (size_t)tab.n_terms * 2 * prec * a.lu;
+        a.t = t ? t + p0 : nullptr;
+        a.x = x + p0;
+        a.val = val + p0;
+        a.jac = jac ? jac + p0 : nullptr;
+        int rc;
+        switch (prec) {
+        case 1: rc = unfused_run<1>(tab, a, st); break;
+        case 2: rc = unfused_run<2>(tab, a, st); break;
+        default: rc = unfused_run<4>(tab, a, st); break;
+        }
+        if (rc) return rc;
     }
+    return PH_OK;
 }
 
 }  // namespace ph

@@ -34,6 +34,8 @@ def _gpu():
 def _run(sysm, L, x, t, gamma, start=None, jac=True, ld=None):
     S = ph.System(sysm)
     G = ph.System(start) if start is not None else None
+    if G is not None:
+        ph.eval_prepare(S, L, start=G)
     import torch
     npts = x.shape[0]
     xs = ph.to_soa(x, ld)
@@ -257,3 +259,148 @@ def test_eval_paper_shaped_stand_ins(name, L):
     ev, ej = scaled_error(v, ov, sv), scaled_error(j, oj, sj)
     print(f"[gpu] shaped {name} L={L}: val_err/S={ev:.2e} jac_err/S={ej:.2e}", flush=True)
     assert ev <= TOL[L] and ej <= TOL[L]
+
+
+def _exp_system(seed, n, exps, terms=10, kmax=5):
+    """n equations, ``terms`` terms each over up to kmax distinct variables,
+    exponents drawn from ``exps`` (every value used at least once), unit
+    coefficients."""
+    rng = np.random.default_rng(seed)
+    eqs, used = [], set()
+    for i in range(n):
+        eq = []
+        for t in range(terms):
+            k = int(rng.integers(1, kmax + 1))
+            vs = rng.choice(n, size=k, replace=False)
+            mono = {int(v): int(rng.choice(exps)) for v in vs}
+            if t < len(exps) and i == 0:
+                mono[int(vs[0])] = int(exps[t])           # every exponent occurs
+            used.update(mono.values())
+            eq.append((synth.unit_complex(rng), mono))
+        eq.append((synth.unit_complex(rng), {}))
+        eqs.append(eq)
+    assert used == set(exps)
+    return synth.system_from_terms(n, eqs)
+
+
+# exponents 1..4 take the double fast path (x^3 plane for a = 4); 5, 8 and 64
+# fall back to the register-row and general kernels
+EXP_SETS = {"a<=4": (1, 2, 3, 4), "a=5,8,64": (1, 5, 8, 64)}
+
+
+@pytest.mark.parametrize("L", LIMBS)
+@pytest.mark.parametrize("which", list(EXP_SETS))
+def test_eval_high_exponents_every_kernel_and_tiling(L, which):
+    """Terms with exponents 4, 5, 8 and 64 (ph.h accepts 1..64) on the unit
+    torus, 151 points (two full tiles and a ragged one), in every kernel the
+    library can run for them and every (waves, groups) the autotuner may pick,
+    against the oracle."""
+    import torch
+    s = _exp_system(60 + len(which), 8, EXP_SETS[which])
+    g = synth.gamma_of(synth.tracking_small())
+    npts = 64 * 2 + 23
+    x, t = synth.torus_points(s, npts, L, np.random.default_rng(61))
+    ov, oj, sv, sj = oracle.eval_homotopy(s, L, x, t, g)
+    S = ph.System(s)
+    xs = ph.to_soa(x)
+    tt = torch.as_tensor(t, dtype=torch.float64).cuda()
+    kernels = [ph.EVAL_FAST, ph.EVAL_FAST_VECROW, ph.EVAL_REGROW, ph.EVAL_GENERAL] if L == 1 \
+        else [ph.EVAL_GENERAL]
+    ran, worst = set(), 0.0
+    for k in kernels:
+        for W in (1, 2, 4, 6, 8):
+            for G in (1, 2, 4, 8):
+                if W * G > s.n_eq:
+                    continue
+                ph.eval_set_config(S, L, k, W, G)
+                try:
+                    val, jm = ph.eval_jac(S, xs, npts, L, tt, g)
+                except ph.PHError as e:
+                    assert "-4" in str(e) and k in (ph.EVAL_FAST, ph.EVAL_FAST_VECROW) \
+                        and which != "a<=4", (k, str(e))
+                    break
+                torch.cuda.synchronize()
+                v = ph.from_soa(val, npts, (s.n_eq, 2, L))
+                j = ph.from_soa(jm, npts, (s.n_eq, s.n_var, 2, L))
+                e = max(scaled_error(v, ov, sv), scaled_error(j, oj, sj))
+                worst = max(worst, e)
+                assert e <= TOL[L], (which, k, W, G, e)
+                ran.add(k)
+    ph.eval_set_config(S, L)
+    print(f"[gpu] exponents {which} L={L}: kernels {sorted(ran)}, worst err/S={worst:.2e}", flush=True)
+    if L == 1:
+        assert ph.EVAL_REGROW in ran and ph.EVAL_GENERAL in ran
+        assert (ph.EVAL_FAST in ran) == (which == "a<=4")
+
+
+def test_values_only_after_autotune():
+    """After ph_eval_autotune picks a register-row kernel (which needs the
+    Jacobian), a values-only call runs the general kernel with the same tiling
+    and matches the oracle."""
+    import torch
+    s = synth.eval_dense(seed=901, n=16, terms_per_eq=12, k=5)
+    g = synth.gamma_of(s)
+    npts = 64 * 5 + 11
+    x, t = synth.torus_points(s, npts, 1, np.random.default_rng(62))
+    S = ph.System(s)
+    xs = ph.to_soa(x)
+    tt = torch.as_tensor(t, dtype=torch.float64).cuda()
+    ph.eval_autotune(S, xs, npts, 1, tt, g)
+    kern = ph.eval_get_config(S, 1)[0]
+    assert kern in (ph.EVAL_FAST, ph.EVAL_FAST_VECROW, ph.EVAL_REGROW, ph.EVAL_GENERAL)
+    val, none = ph.eval_jac(S, xs, npts, 1, tt, g, want_jac=False)
+    torch.cuda.synchronize()
+    assert none is None
+    ov, _, sv, _ = oracle.eval_homotopy(s, 1, x, t, g, jac=False)
+    e = scaled_error(ph.from_soa(val, npts, (s.n_eq, 2, 1)), ov, sv)
+    print(f"[gpu] values only after autotune (kernel {kern}): err/S={e:.2e}", flush=True)
+    assert e <= TOL[1]
+
+
+@pytest.mark.parametrize("L", [1, 2])
+def test_eval_with_new_start_system_in_a_graph(L):
+    """ph_eval_jac with a start system prepared beforehand neither allocates
+    nor synchronises, so it can be captured in a HIP graph: capture it once,
+    replay it three times with eager work (new points written) in between, and
+    compare every replay with an eager call and the oracle.  An unprepared
+    start system is refused."""
+    import torch
+    s = synth.tracking_cubic()
+    deg = s.degrees()
+    gsys = synth.system_from_terms(s.n_var, [[(1.0 - 0.5j, {i: int(deg[i])}), (-1, {}),
+                                              (0.25, {(i + 3) % s.n_var: 1})] for i in range(s.n_eq)])
+    S, G = ph.System(s), ph.System(gsys)
+    gam = synth.gamma_of(s)
+    npts = 64 * 3 + 5
+    rng = np.random.default_rng(63)
+    xs = ph.to_soa(synth.random_points(s.n_var, npts, L, rng))
+    tt = torch.as_tensor(rng.uniform(0, 1, npts), dtype=torch.float64).cuda()
+    with pytest.raises(ph.PHError, match="-1"):
+        ph.eval_jac(S, xs, npts, L, tt, gam, start=G)
+    ph.eval_prepare(S, L, start=G)
+    val = torch.empty((s.n_eq * 2 * L, npts), dtype=torch.float64, device="cuda")
+    jac = torch.empty((s.n_eq * s.n_var * 2 * L, npts), dtype=torch.float64, device="cuda")
+    ph.eval_jac(S, xs, npts, L, tt, gam, start=G, val=val, jac=jac)   # warm-up, module load
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        ph.eval_jac(S, xs, npts, L, tt, gam, start=G, val=val, jac=jac)
+    for rep in range(3):
+        x = synth.random_points(s.n_var, npts, L, rng)
+        t = rng.uniform(0, 1, npts)
+        xs.copy_(ph.to_soa(x))
+        tt.copy_(torch.as_tensor(t, dtype=torch.float64))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        v_g, j_g = val.clone(), jac.clone()
+        v_e, j_e = ph.eval_jac(S, xs, npts, L, tt, gam, start=G)
+        torch.cuda.synchronize()
+        assert torch.equal(v_g, v_e) and torch.equal(j_g, j_e), rep
+        idx = np.array([0, 70, npts - 1])
+        ov, oj, sv, sj = oracle.eval_homotopy(s, L, x[idx], t[idx], gam, start=gsys)
+        it = torch.as_tensor(idx, device="cuda")
+        v = v_g[:, it].T.contiguous().cpu().numpy().reshape(len(idx), s.n_eq, 2, L)
+        j = j_g[:, it].T.contiguous().cpu().numpy().reshape(len(idx), s.n_eq, s.n_var, 2, L)
+        assert max(scaled_error(v, ov, sv), scaled_error(j, oj, sj)) <= TOL[L], rep
+    print(f"[gpu] graph-captured eval with a prepared start system L={L}: 3 replays ok", flush=True)

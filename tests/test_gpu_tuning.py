@@ -46,6 +46,7 @@ def test_every_configuration_matches_oracle(L):
     kernels = [ph.EVAL_GENERAL, ph.EVAL_UNFUSED] + ([ph.EVAL_REGROW, ph.EVAL_FAST, ph.EVAL_FAST_VECROW]
                                                    if L == 1 else [])
     worst = 0.0
+    ph.eval_prepare(S, L, unfused_points=npts)
     for k in kernels:
         tilings = [(0, 0)] if k == ph.EVAL_UNFUSED else [(W, G) for W in (1, 2, 4, 8) for G in (1, 2, 4)]
         for W, G in tilings:
@@ -63,13 +64,17 @@ def test_every_configuration_matches_oracle(L):
 @pytest.mark.parametrize("L", [1, 2, 4])
 def test_unfused_design_long_terms_and_values_only(L):
     """The paper's three-kernel design on a system with terms of 10 factors
-    (the cyclic10-shaped stand-in), with and without the Jacobian, and on a
-    second, larger call that regrows its intermediate arrays."""
+    (the cyclic10-shaped stand-in), with and without the Jacobian; refused
+    before ph_eval_prepare sized its arrays, and on a second, larger call run
+    in two chunks of the prepared capacity."""
     import torch
     s = synth.SHAPED["cyclic10"]()
     g = synth.gamma_of(s)
     S = ph.System(s)
     ph.eval_set_config(S, L, ph.EVAL_UNFUSED)
+    with pytest.raises(ph.PHError, match="-1"):          # arrays not sized yet
+        _eval(S, s, L, *synth.torus_points(s, 5, L, np.random.default_rng(1)), g)
+    ph.eval_prepare(S, L, unfused_points=70)              # 128 points per chunk
     for npts in (70, 200):
         rng = np.random.default_rng(40 + npts)
         x, t = synth.torus_points(s, npts, L, rng)

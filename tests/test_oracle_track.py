@@ -20,6 +20,7 @@ import pytest
 import oracle
 from paper_1505_00383_amd import synth
 from tests.exact import frc, limb_sum_diff
+from tests.starts import diagonal_roots, diagonal_start
 
 U = {1: 2.0 ** -53, 2: 2.0 ** -104, 4: 2.0 ** -208}
 
@@ -324,35 +325,6 @@ def test_singular_flag_quad_double():
 # ---------------------------------------------------------------------------
 # Explicit start systems g (Eq. (1) allows any g with known roots)
 # ---------------------------------------------------------------------------
-def _diagonal_start(rng, deg):
-    """g_i = a_i x_i^{d_i} - b_i with random complex a_i, b_i: not the
-    total-degree start system, roots x_i = (b_i / a_i)^{1/d_i} omega^k in
-    closed form (computed here in mpmath, not by the oracle)."""
-    a = [synth.unit_complex(rng) * (0.5 + rng.uniform()) for _ in deg]
-    b = [synth.unit_complex(rng) * (0.5 + rng.uniform()) for _ in deg]
-    g = synth.system_from_terms(len(deg), [[(a[i], {i: int(d)}), (-b[i], {})] for i, d in enumerate(deg)])
-    return g, a, b
-
-
-def _diagonal_roots(a, b, deg, L, paths):
-    import mpmath
-    mpmath.mp.dps = 80
-    X = np.zeros((len(paths), len(deg), 2, L))
-    for q, p in enumerate(paths):
-        rem = int(p)
-        for i, d in enumerate(deg):
-            k = rem % int(d)
-            rem //= int(d)
-            z = mpmath.root(mpmath.mpc(b[i].real, b[i].imag) / mpmath.mpc(a[i].real, a[i].imag), int(d), k)
-            for c, part in enumerate((z.real, z.imag)):
-                r = part
-                for l in range(L):
-                    v = float(r)
-                    X[q, i, c, l] = v
-                    r -= mpmath.mpf(v)
-    return X
-
-
 @pytest.mark.parametrize("L", [1, 2, 4])
 def test_custom_start_f_equals_g_stays_put(L):
     """f = g for a start system that is not x^d - 1: H = (gamma(1-t) + t) g, so
@@ -360,9 +332,9 @@ def test_custom_start_f_equals_g_stays_put(L):
     rounding of its limbs; the endpoint must be that root to ~u_L."""
     rng = np.random.default_rng(31)
     deg = [2, 3, 2]
-    g, a, b = _diagonal_start(rng, deg)
+    g, a, b = diagonal_start(rng, deg)
     paths = np.arange(12)
-    X0 = _diagonal_roots(a, b, deg, L, paths)
+    X0 = diagonal_roots(a, b, deg, L, paths)
     r = oracle.track(g, complex(np.cos(0.4), np.sin(0.4)), paths, oracle.Opts(prec=L), start=g, x0=X0)
     assert np.all(r["status"] == 1)
     d = np.abs(limb_sum_diff(r["x"], X0)).max()
@@ -379,8 +351,8 @@ def test_custom_start_reaches_the_same_endpoints(L):
     gam = synth.gamma_of(s)
     rng = np.random.default_rng(41)
     deg = [2, 2, 2]
-    g, a, b = _diagonal_start(rng, deg)
-    X0 = _diagonal_roots(a, b, deg, L, np.arange(8))
+    g, a, b = diagonal_start(rng, deg)
+    X0 = diagonal_roots(a, b, deg, L, np.arange(8))
     custom = oracle.track(s, gam, np.arange(8), oracle.Opts(prec=L), start=g, x0=X0)
     total = oracle.track(s, gam, range(8), oracle.Opts(prec=L))
     assert np.all(custom["status"] == 1) and np.all(total["status"] == 1)

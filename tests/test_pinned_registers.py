@@ -3,7 +3,9 @@ compiler is told it may not use (a register budget plus clobbers on every
 statement that touches them).  Compile the evaluation source to gfx950
 assembly and check that no compiler-generated instruction touches the
 pinned registers, that nothing spills to scratch, and that the kernel
-descriptor reserves the pinned registers."""
+descriptor reserves the pinned registers.  The GPR indexing mode those
+statements use writes M0, which the compiler reserves (a clobber of it is not
+honoured): no compiler-generated instruction of these kernels may use M0."""
 import os
 import re
 import shutil
@@ -43,5 +45,7 @@ def test_pinned_registers_untouched_by_compiler(asm, pattern, first_pinned, vgpr
            if any(int(m.group(2) or m.group(3)) >= first_pinned
                   for m in re.finditer(r"v\[(\d+):(\d+)\]|\bv(\d+)\b", ln))]
     assert not bad, bad[:5]
+    m0 = [ln for ln in outside.split("\n") if re.search(r"\bm0\b", ln)]
+    assert not m0, m0[:5]
     assert re.search(r"; ScratchSize: (\S+)", tail).group(1) == "0"
     assert re.search(r"; NumVgprs: (\S+)", tail).group(1) == vgprs
