@@ -103,6 +103,52 @@ def bytes_per_point(sysm, L):
     return 16 * L * (n + m + m * n) + 8
 
 
+def host_info():
+    """Host cores the oracle may use and the CPU model (stated beside every
+    oracle rate)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return {"nproc": avail, "cpu_count": os.cpu_count(), "model": model,
+            "threads_used": min(16, avail)}
+
+
+def mgs_flops(n, L):
+    """FP64 flops of one least-squares Newton solve by MGS on the n x (n+1)
+    augmented complex matrix [J | -H] in L limbs (the mixed scheme: L = 1),
+    with its back substitution: n^2 (n+1) + n(n-1)/2 complex products and
+    additions (projections, updates, back substitution), n^2 + n complex-by-
+    real scalings (normalisation, division by r_kk), n^2 squared moduli."""
+    cm = n * n * (n + 1) + n * (n - 1) // 2
+    return cm * (CMUL[L] + CADD[L]) + (n * n + n) * CSCALE[L] + n * n * (CSCALE[L] + CADD[L] // 2)
+
+
+def track_iteration_flops(sysm, L, mixed):
+    """One evaluate-correct step of a path: H and J of the homotopy at one point
+    in L limbs, the MGS solve (FP64 when mixed), the update of x in L limbs,
+    and the FP64 norms of the convergence test."""
+    n = sysm.n_var
+    return flops_per_point(sysm, L) + mgs_flops(n, 1 if mixed else L) + n * CADD[L] + n * n + 4 * n
+
+
+def predictor_flops(sysm, L, order):
+    """One predictor step per path: the secant x + r (x - x_p) is one complex
+    subtraction, scaling and addition per coordinate; order m >= 2 scales and
+    adds m + 1 points."""
+    n = sysm.n_var
+    return n * (2 * CADD[L] + CSCALE[L]) if order <= 1 else n * (order + 1) * (CSCALE[L] + CADD[L])
+
+
 def cpu_baseline(sysm, L, x, t, gamma, target_s=15.0):
     import oracle
     threads = min(16, os.cpu_count() or 1)
@@ -120,10 +166,11 @@ def cpu_baseline(sysm, L, x, t, gamma, target_s=15.0):
     t0 = time.perf_counter()
     oracle.eval_homotopy(sysm, L, x[:m1], t[:m1], gamma, scales=False)
     one_rate = m1 / (time.perf_counter() - t0)
+    hi = host_info()
     return {"value": npts / wall, "unit": "points/s", "cores": threads, "kind": "oracle",
             "sample": f"first {npts} of the 65536 points, {PREC_NAME[L]}, {threads} host threads "
                       f"over contiguous point ranges, {wall:.1f} s wall; one core: first {m1} points",
-            "one_core_value": one_rate}
+            "one_core_value": one_rate, "host": hi}
 
 
 def time_eval(ph, torch, S, sysm, L, npts, steps, warmup, gamma, rng=None, inputs=None):
@@ -148,8 +195,19 @@ def time_eval(ph, torch, S, sysm, L, npts, steps, warmup, gamma, rng=None, input
     return ms, ok, x, t
 
 
+def track_roofline(sysm, L, mixed, order, rep, seconds, npaths):
+    """Algorithmic FP64 flops per path from the device counters (Newton
+    iterations and predictor steps, polish included) and the tracker's
+    fraction of the FP64 vector peak."""
+    it = track_iteration_flops(sysm, L, mixed)
+    fl = rep["newton_its"] * it + rep["steps"] * predictor_flops(sysm, L, order)
+    return {"flops_per_iteration": it, "flops_per_path": fl / max(npaths, 1),
+            "achieved_TFLOPs": fl / seconds / 1e12, "fp64_frac": fl / seconds / PEAK_FP64}
+
+
 def time_track(ph, torch, sysm, L, mixed, npaths, reps=1, order=1):
-    """paths/s of ph_track on the first npaths start solutions (roots of unity)."""
+    """paths/s of ph_track on the first npaths start solutions (roots of unity),
+    with the tracker's algorithmic flops and roofline fraction."""
     from paper_1505_00383_amd import synth
     S = ph.System(sysm)
     g = synth.gamma_of(sysm)
@@ -173,7 +231,65 @@ def time_track(ph, torch, sysm, L, mixed, npaths, reps=1, order=1):
                 k: int(rep[k]) for k in ("n_diverged", "n_step_underflow", "n_max_steps",
                                          "n_singular", "n_nan")},
             "steps_per_path": rep["steps"] / max(npaths, 1),
-            "newton_per_path": rep["newton_its"] / max(npaths, 1)}, res
+            "newton_per_path": rep["newton_its"] / max(npaths, 1),
+            "roofline": track_roofline(sysm, L, mixed, order, rep, sec, npaths)}, res
+
+
+def _limb_err(xg, xr):
+    """||xg - xr||_inf / max(1, ||xr||_inf) per path for [p, n, 2, L] limb arrays,
+    each limb difference summed exactly (math.fsum) before rounding."""
+    import math
+    p, n = xg.shape[0], xg.shape[1]
+    out = np.zeros(p)
+    for k in range(p):
+        worst, big = 0.0, 1.0
+        for i in range(n):
+            dre = math.fsum(list(xg[k, i, 0]) + [-v for v in xr[k, i, 0]])
+            dim = math.fsum(list(xg[k, i, 1]) + [-v for v in xr[k, i, 1]])
+            worst = max(worst, math.hypot(dre, dim))
+            big = max(big, math.hypot(xr[k, i, 0].sum(), xr[k, i, 1].sum()))
+        out[k] = worst / big
+    return out
+
+
+def oracle_track_rate(sysm, gamma, L, mixed, paths, threads):
+    """The oracle's tracker (plain C, expansion arithmetic) on the listed start
+    paths with `threads` host threads; returns (paths/s, result)."""
+    import oracle
+    t0 = time.perf_counter()
+    r = oracle.track(sysm, gamma, np.asarray(paths), oracle.Opts(prec=L, mixed=mixed), threads=threads)
+    return len(paths) / (time.perf_counter() - t0), r
+
+
+def oracle_beside(sysm, gamma, L, mixed, one_paths, all_paths, gpu_res=None, gpu_paths=None):
+    """One-core and all-core oracle tracking rates on stated path subsets, and,
+    for a mixed GPU run, the error of every GPU endpoint of the all-core
+    subset against the oracle's PLAIN track in the same precision."""
+    import paper_1505_00383_amd as ph
+    hi = host_info()
+    thr = hi["threads_used"]
+    r1, _ = oracle_track_rate(sysm, gamma, L, mixed, one_paths, 1)
+    ref_mixed = mixed if gpu_res is None else 0            # endpoint errors: plain reference
+    ra, ref = oracle_track_rate(sysm, gamma, L, ref_mixed, all_paths, thr)
+    out = {"oracle_1core_paths_per_s": r1, "oracle_1core_sample": f"paths {list(map(int, one_paths))}",
+           "oracle_1core_mixed": int(mixed),
+           "oracle_allcores_paths_per_s": ra, "oracle_allcores_threads": thr,
+           "oracle_allcores_sample": f"{len(all_paths)} paths (every {max(1, int(all_paths[1] - all_paths[0])) if len(all_paths) > 1 else 1}th from {int(all_paths[0])})",
+           "oracle_allcores_mixed": int(ref_mixed)}
+    if gpu_res is not None:
+        import torch
+        pos = np.searchsorted(gpu_paths, all_paths)
+        it = torch.as_tensor(pos, device="cuda")
+        xg = ph.from_soa(gpu_res["x_end"][:, it], len(pos), (sysm.n_var, 2, L))
+        st = gpu_res["status"][pos]
+        ok = (st == 1) & (ref["status"] == 1)
+        err = _limb_err(xg[ok], ref["x"][ok]) if ok.any() else np.zeros(0)
+        out["mixed_endpoint_error_vs_oracle_plain"] = {
+            "paths": int(len(pos)), "both_succeeded": int(ok.sum()),
+            "status_agree": int(np.sum(st == ref["status"])),
+            "max": float(err.max()) if err.size else None,
+            "median": float(np.median(err)) if err.size else None}
+    return out
 
 
 def endpoint_agreement(ph, a, b, n, L, npaths, tol):
@@ -184,7 +300,24 @@ def endpoint_agreement(ph, a, b, n, L, npaths, tol):
     return float(np.mean(ok & (d <= tol)))
 
 
-def time_batch(ph, torch, systems, gammas, paths, opts):
+def batch_roofline(sysms, res, order, seconds, L=2, mixed=1):
+    """Algorithmic flops of a batch: every path's predictor steps (device
+    array) times its system's cost per step, the Newton iterations spread over
+    the steps at the batch's measured ratio (the device counts them in total)."""
+    rep = res["report"]
+    off = res["path_off"]
+    steps = res["steps"].astype(np.float64)
+    ratio = rep["newton_its"] / max(rep["steps"], 1)
+    fl = 0.0
+    for k, sy in enumerate(sysms):
+        st_k = steps[off[k]:off[k + 1]].sum()
+        fl += st_k * (ratio * track_iteration_flops(sy, L, mixed) + predictor_flops(sy, L, order))
+    total = int(off[-1])
+    return {"flops_per_path": fl / max(total, 1), "achieved_TFLOPs": fl / seconds / 1e12,
+            "fp64_frac": fl / seconds / PEAK_FP64}
+
+
+def time_batch(ph, torch, systems, gammas, paths, opts, sysms=None):
     st = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(st)
@@ -194,15 +327,62 @@ def time_batch(ph, torch, systems, gammas, paths, opts):
     sec = e0.elapsed_time(e1) * 1e-3
     rep = res["report"]
     total = int(res["path_off"][-1])
-    return {"paths": total, "seconds": sec, "paths_per_s": total / sec,
-            "success": int(rep["n_success"]), "failed_by_reason": {
-                k: int(rep[k]) for k in ("n_diverged", "n_step_underflow", "n_max_steps",
-                                         "n_singular", "n_nan")},
-            "steps_per_path": rep["steps"] / max(total, 1),
-            "newton_per_path": rep["newton_its"] / max(total, 1)}
+    out = {"paths": total, "seconds": sec, "paths_per_s": total / sec,
+           "success": int(rep["n_success"]), "failed_by_reason": {
+               k: int(rep[k]) for k in ("n_diverged", "n_step_underflow", "n_max_steps",
+                                        "n_singular", "n_nan")},
+           "steps_per_path": rep["steps"] / max(total, 1),
+           "newton_per_path": rep["newton_its"] / max(total, 1)}
+    if sysms is not None:
+        out["roofline"] = batch_roofline(sysms, res, opts.predictor_order, sec, opts.prec, opts.mixed)
+    return out, res
 
 
-def batch_extra(ph, torch):
+def batch_oracle(sysms, gammas, paths, res):
+    """The oracle on (system, path) pairs sampled across the batch: one core in
+    the GPU run's mode (DD residual, FP64 solves), all host cores in plain DD,
+    whose endpoints are the reference for the GPU's mixed endpoints."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    import paper_1505_00383_amd as ph
+    import torch
+    hi = host_info()
+    thr = hi["threads_used"]
+    rng = np.random.default_rng(99)
+    pairs = [(int(k), int(rng.integers(0, len(paths[k])))) for k in rng.choice(len(sysms), 2 * thr)]
+
+    def one(pr, mixed):
+        k, j = pr
+        return oracle.track(sysms[k], gammas[k], paths[k][j:j + 1], oracle.Opts(prec=2, mixed=mixed))
+
+    t0 = time.perf_counter()
+    for pr in pairs[:4]:
+        one(pr, 1)
+    r1 = 4 / (time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(thr) as ex:
+        refs = list(ex.map(lambda pr: one(pr, 0), pairs))
+    ra = len(pairs) / (time.perf_counter() - t0)
+    off = res["path_off"]
+    errs, agree = [], 0
+    for (k, j), ref in zip(pairs, refs):
+        gi = int(off[k]) + j
+        n = sysms[k].n_var
+        xg = ph.from_soa(res["x_end"][:n * 2 * 2, gi:gi + 1], 1, (n, 2, 2))
+        agree += int(res["status"][gi] == ref["status"][0])
+        if res["status"][gi] == 1 and ref["status"][0] == 1:
+            errs.append(_limb_err(xg, ref["x"])[0])
+    errs = np.array(errs)
+    return {"oracle_1core_paths_per_s": r1, "oracle_1core_sample": "4 sampled (system, path) pairs, DD mixed",
+            "oracle_allcores_paths_per_s": ra, "oracle_allcores_threads": thr,
+            "oracle_allcores_sample": f"{len(pairs)} sampled (system, path) pairs, plain DD",
+            "mixed_endpoint_error_vs_oracle_plain": {
+                "paths": len(pairs), "both_succeeded": int(errs.size), "status_agree": agree,
+                "max": float(errs.max()) if errs.size else None,
+                "median": float(np.median(errs)) if errs.size else None}}
+
+
+def batch_extra(ph, torch, cpu=True):
     """64 systems, n ~ U{4..16}, d ~ U{2,3}, 8..32 terms per equation, about
     200k paths in one launch, DD residual with FP64 Newton solves; the launch
     shape is autotuned on a 16384-path sample, then the whole batch runs
@@ -221,9 +401,11 @@ def batch_extra(ph, torch):
            "tuned": {"schedule": "graph" if tuned.schedule == ph.SCHED_GRAPH else "persistent",
                      "rounds_per_launch": tuned.rounds_per_launch,
                      "blocks_per_cu": tuned.blocks_per_cu, "sample_seconds": tsec}}
-    out["tuned_run"] = time_batch(ph, torch, systems, gammas, paths, tuned)
-    out["graph"] = time_batch(ph, torch, systems, gammas, paths, graph)
-    out["persistent_default"] = time_batch(ph, torch, systems, gammas, paths, base)
+    out["tuned_run"], res = time_batch(ph, torch, systems, gammas, paths, tuned, sysms)
+    out["graph"], _ = time_batch(ph, torch, systems, gammas, paths, graph, sysms)
+    out["persistent_default"], _ = time_batch(ph, torch, systems, gammas, paths, base, sysms)
+    if cpu:
+        out["oracle"] = batch_oracle(sysms, gammas, paths, res)
     return out
 
 
@@ -345,22 +527,35 @@ def paper_shaped_extra(ph, torch, cpu_seconds=1.0):
     return out
 
 
-def tracking_extras(ph, torch):
+def tracking_extras(ph, torch, cpu=True):
+    """Tracking on the four tracking workloads: paths/s, algorithmic flops per
+    path and roofline fraction (device counters), mixed vs plain, and the
+    oracle timed beside it on stated path subsets (one core and all host
+    cores), with the error of every mixed endpoint of the subset against the
+    oracle's plain track in the same precision."""
     from paper_1505_00383_amd import synth
     out = {}
+    thr = host_info()["threads_used"]
     small = synth.tracking_small()
     d_small, _ = time_track(ph, torch, small, 1, 0, 8, reps=3)
+    if cpu:
+        d_small["oracle"] = oracle_beside(small, synth.gamma_of(small), 1, 0, np.arange(8), np.arange(8))
     out["track_n3_d2_8paths_double"] = d_small
     cub = synth.tracking_cubic()
+    gc = synth.gamma_of(cub)
     B = 3 ** 8
     dd_m, r_m = time_track(ph, torch, cub, 2, 1, B, reps=2)
     dd_p, r_p = time_track(ph, torch, cub, 2, 0, B, reps=2)
     d_p, _ = time_track(ph, torch, cub, 1, 0, B, reps=2)
-    out["track_n8_d3_6561paths"] = {
-        "double_plain": d_p, "dd_mixed": dd_m, "dd_plain": dd_p,
-        "dd_mixed_over_plain": dd_m["paths_per_s"] / dd_p["paths_per_s"],
-        "dd_endpoint_agreement_1e-24": endpoint_agreement(ph, r_m, r_p, 8, 2, B, 1e-24)}
+    row = {"double_plain": d_p, "dd_mixed": dd_m, "dd_plain": dd_p,
+           "dd_mixed_over_plain": dd_m["paths_per_s"] / dd_p["paths_per_s"],
+           "dd_endpoint_agreement_1e-24": endpoint_agreement(ph, r_m, r_p, 8, 2, B, 1e-24)}
+    if cpu:
+        sub = np.arange(4 * thr) * (B // (4 * thr))
+        row["oracle"] = oracle_beside(cub, gc, 2, 1, np.arange(6), sub, r_m, np.arange(B))
+    out["track_n8_d3_6561paths"] = row
     q16 = synth.tracking_quadratic16()
+    gq = synth.gamma_of(q16)
     sub = 4096
     qd_m, q_m = time_track(ph, torch, q16, 4, 1, sub)
     qd_p, q_p = time_track(ph, torch, q16, 4, 0, sub)
@@ -368,7 +563,10 @@ def tracking_extras(ph, torch):
         "qd_mixed": qd_m, "qd_plain": qd_p,
         "qd_mixed_over_plain": qd_m["paths_per_s"] / qd_p["paths_per_s"],
         "qd_endpoint_agreement_1e-48": endpoint_agreement(ph, q_m, q_p, 16, 4, sub, 1e-48)}
-    full, _ = time_track(ph, torch, q16, 4, 1, 2 ** 16)
+    full, r_full = time_track(ph, torch, q16, 4, 1, 2 ** 16)
+    if cpu:
+        sub16 = np.arange(thr) * (2 ** 16 // thr)
+        full["oracle"] = oracle_beside(q16, gq, 4, 1, np.arange(2), sub16, r_full, np.arange(2 ** 16))
     out["track_n16_d2_qd_mixed_65536paths"] = full
     # the fourth-order predictor (current and four previous points)
     c4, _ = time_track(ph, torch, cub, 2, 1, B, reps=2, order=4)
@@ -542,14 +740,71 @@ def main():
         extras["eval_n16_d2_hbm_1M_points_double"] = hbm_extra(ph, torch, max(3, args.steps // 4))
         extras["eval_pcie_inclusive_host_buffers"] = pcie_extra(ph, torch, S, sysm, L, npts, gamma)
         extras["unfused_three_kernel_ablation"] = unfused_extra(ph, torch, S, sysm, gamma, 5)
-        extras.update(tracking_extras(ph, torch))
-        extras["track_batch64_dd_mixed"] = batch_extra(ph, torch)
+        extras.update(tracking_extras(ph, torch, cpu=not args.no_cpu_baseline))
+        extras["track_batch64_dd_mixed"] = batch_extra(ph, torch, cpu=not args.no_cpu_baseline)
         if not args.no_cpu_baseline:
             extras["paper_shaped_eval"] = paper_shaped_extra(ph, torch)
         result["extras"] = extras
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(sysm, L, x, t, gamma)
+    # the compact per-precision summary comes last, so a truncated log keeps it
+    result["summary"] = summary(result, L)
     print(json.dumps(result))
+
+
+def summary(result, L):
+    """Every cell of the metric in one place: evaluation points/s and FP64
+    fraction per precision, tracking paths/s and FP64 fraction per workload
+    (mixed and plain), the oracle's tracking rates beside them, and the
+    error of the mixed endpoints against the oracle's plain track."""
+    name = {1: "D", 2: "DD", 4: "QD"}
+    ex = result.get("extras", {})
+    out = {"eval_points_per_s": {name[L]: result["value"]},
+           "eval_fp64_frac": {name[L]: result["roofline"]["frac"]}}
+    for L2 in (1, 2, 4):
+        e = ex.get(f"eval_prec{L2}")
+        if e:
+            out["eval_points_per_s"][name[L2]] = e["points_per_s"]
+            out["eval_fp64_frac"][name[L2]] = e["fp64_frac"]
+    runs = {}
+    if "track_n3_d2_8paths_double" in ex:
+        runs["n3_d2_8p_D_plain"] = ex["track_n3_d2_8paths_double"]
+    c = ex.get("track_n8_d3_6561paths", {})
+    for k, lab in (("double_plain", "n8_d3_6561p_D_plain"), ("dd_mixed", "n8_d3_6561p_DD_mixed"),
+                   ("dd_plain", "n8_d3_6561p_DD_plain")):
+        if k in c:
+            runs[lab] = c[k]
+    q = ex.get("track_n16_d2_qd_4096paths", {})
+    for k, lab in (("qd_mixed", "n16_d2_4096p_QD_mixed"), ("qd_plain", "n16_d2_4096p_QD_plain")):
+        if k in q:
+            runs[lab] = q[k]
+    if "track_n16_d2_qd_mixed_65536paths" in ex:
+        runs["n16_d2_65536p_QD_mixed"] = ex["track_n16_d2_qd_mixed_65536paths"]
+    b = ex.get("track_batch64_dd_mixed", {})
+    if "tuned_run" in b:
+        runs["batch64_200kp_DD_mixed"] = b["tuned_run"]
+    if runs:
+        out["track_paths_per_s"] = {k: v["paths_per_s"] for k, v in runs.items()}
+        out["track_fp64_frac"] = {k: v["roofline"]["fp64_frac"] for k, v in runs.items() if "roofline" in v}
+    orc = {"n3_d2_D": ex.get("track_n3_d2_8paths_double", {}).get("oracle"),
+           "n8_d3_DD": c.get("oracle"),
+           "n16_d2_QD": ex.get("track_n16_d2_qd_mixed_65536paths", {}).get("oracle"),
+           "batch64_DD": b.get("oracle")}
+    orc = {k: v for k, v in orc.items() if v}
+    if orc:
+        out["oracle_track_paths_per_s"] = {
+            k: {"1core": v["oracle_1core_paths_per_s"], "allcores": v["oracle_allcores_paths_per_s"],
+                "threads": v["oracle_allcores_threads"]} for k, v in orc.items()}
+        out["mixed_endpoint_err_vs_oracle_plain"] = {
+            k: {"max": v["mixed_endpoint_error_vs_oracle_plain"]["max"],
+                "median": v["mixed_endpoint_error_vs_oracle_plain"]["median"],
+                "paths": v["mixed_endpoint_error_vs_oracle_plain"]["paths"]}
+            for k, v in orc.items() if "mixed_endpoint_error_vs_oracle_plain" in v}
+    if "cpu_baseline" in result:
+        out["oracle_eval_points_per_s"] = {"allcores": result["cpu_baseline"]["value"],
+                                           "1core": result["cpu_baseline"]["one_core_value"]}
+        out["host"] = result["cpu_baseline"].get("host")
+    return out
 
 
 if __name__ == "__main__":

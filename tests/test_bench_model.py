@@ -64,3 +64,51 @@ def test_traffic_guard(monkeypatch):
     assert bench.traffic_of("k_tiled") is None
     assert bench.traffic_of("k_stale") is None
     assert bench.traffic_of("unknown") is None
+
+
+def test_mgs_flops_counts_by_hand():
+    # n = 1: [J | -H] is 1 x 2; column 0: |w|^2 (1 squared modulus), r_00,
+    # q = w / r (1 scaling); column 1: r_01 = q^H w_1 and the update (2
+    # complex products and additions); back substitution dx = r_01 / r_00
+    # (1 scaling): n^2 (n+1) = 2 products and additions, n^2 + n = 2 scalings
+    for L in (1, 2, 4):
+        M, A, S = bench.CMUL[L], bench.CADD[L], bench.CSCALE[L]
+        assert bench.mgs_flops(1, L) == 2 * (M + A) + 2 * S + (S + A // 2)
+    # the cubic growth that makes the plain QD solve dominate at n = 16
+    assert bench.mgs_flops(16, 4) / bench.mgs_flops(16, 1) > 50
+
+
+def test_tracker_cost_model_and_roofline():
+    s = _Sys([[1, 2]], [2, 2])
+    it = bench.track_iteration_flops(s, 2, 1)
+    assert it == bench.flops_per_point(s, 2) + bench.mgs_flops(2, 1) + 2 * bench.CADD[2] + 4 + 8
+    assert bench.track_iteration_flops(s, 2, 0) > it           # plain solves in DD
+    rep = {"newton_its": 300, "steps": 100}
+    r = bench.track_roofline(s, 2, 1, 1, rep, 1e-3, 10)
+    want = 300 * it + 100 * bench.predictor_flops(s, 2, 1)
+    assert abs(r["flops_per_path"] - want / 10) < 1e-9
+    assert abs(r["fp64_frac"] - want / 1e-3 / bench.PEAK_FP64) < 1e-12
+
+
+def test_limb_error_is_exact_on_cancelling_limbs():
+    a = np.zeros((1, 1, 2, 2))
+    b = np.zeros((1, 1, 2, 2))
+    a[0, 0, 0] = [1.0, 2.0 ** -60]
+    b[0, 0, 0] = [1.0, 0.0]
+    assert bench._limb_err(a, b)[0] == 2.0 ** -60
+    assert bench._limb_err(b, b)[0] == 0.0
+
+
+def test_summary_keeps_every_cell_last():
+    res = {"value": 1.0, "roofline": {"frac": 0.5},
+           "extras": {"eval_prec2": {"points_per_s": 2.0, "fp64_frac": 0.4},
+                      "track_n3_d2_8paths_double": {"paths_per_s": 3.0, "roofline": {"fp64_frac": 0.1},
+                                                    "oracle": {"oracle_1core_paths_per_s": 5.0,
+                                                               "oracle_allcores_paths_per_s": 9.0,
+                                                               "oracle_allcores_threads": 2}}},
+           "cpu_baseline": {"value": 7.0, "one_core_value": 1.5, "host": {"nproc": 2}}}
+    out = bench.summary(res, 1)
+    assert out["eval_points_per_s"] == {"D": 1.0, "DD": 2.0}
+    assert out["track_paths_per_s"] == {"n3_d2_8p_D_plain": 3.0}
+    assert out["oracle_track_paths_per_s"]["n3_d2_D"] == {"1core": 5.0, "allcores": 9.0, "threads": 2}
+    assert out["host"] == {"nproc": 2}
