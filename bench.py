@@ -103,6 +103,11 @@ def bytes_per_point(sysm, L):
     return 16 * L * (n + m + m * n) + 8
 
 
+def log(msg):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def host_info():
     """Host cores the oracle may use and the CPU model (stated beside every
     oracle rate)."""
@@ -541,6 +546,7 @@ def tracking_extras(ph, torch, cpu=True):
     if cpu:
         d_small["oracle"] = oracle_beside(small, synth.gamma_of(small), 1, 0, np.arange(8), np.arange(8))
     out["track_n3_d2_8paths_double"] = d_small
+    log("tracking n = 3 done")
     cub = synth.tracking_cubic()
     gc = synth.gamma_of(cub)
     B = 3 ** 8
@@ -554,6 +560,7 @@ def tracking_extras(ph, torch, cpu=True):
         sub = np.arange(4 * thr) * (B // (4 * thr))
         row["oracle"] = oracle_beside(cub, gc, 2, 1, np.arange(6), sub, r_m, np.arange(B))
     out["track_n8_d3_6561paths"] = row
+    log("tracking n = 8 done")
     q16 = synth.tracking_quadratic16()
     gq = synth.gamma_of(q16)
     sub = 4096
@@ -568,6 +575,7 @@ def tracking_extras(ph, torch, cpu=True):
         sub16 = np.arange(thr) * (2 ** 16 // thr)
         full["oracle"] = oracle_beside(q16, gq, 4, 1, np.arange(2), sub16, r_full, np.arange(2 ** 16))
     out["track_n16_d2_qd_mixed_65536paths"] = full
+    log("tracking n = 16 done")
     # the fourth-order predictor (current and four previous points)
     c4, _ = time_track(ph, torch, cub, 2, 1, B, reps=2, order=4)
     f4, _ = time_track(ph, torch, q16, 4, 1, 2 ** 16, order=4)
@@ -678,6 +686,7 @@ def main():
             tuned_cfg = ph.eval_get_config(S, L)
             tuned_by = "ph_eval_autotune"
     ms, ok, x, t = time_eval(ph, torch, S, sysm, L, npts, args.steps, args.warmup, gamma, inputs=(x0, t0))
+    log(f"timed eval prec {L}: {ms:.4f} ms per step")
     if args.kernel:
         ph.eval_set_config(S, L)
     fpp = flops_per_point(sysm, L)
@@ -734,14 +743,19 @@ def main():
             ms2, ok2, _, _ = time_eval(ph, torch, S, sysm, L2, npts, max(3, args.steps // 4), 3, gamma,
                                        inputs=(x2, t2))
             f2 = flops_per_point(sysm, L2)
+            log(f"eval prec {L2}: {ms2:.3f} ms")
             extras[f"eval_prec{L2}"] = {"points_per_s": npts / (ms2 * 1e-3), "ms": ms2,
                                         "fp64_frac": f2 * npts / (ms2 * 1e-3) / PEAK_FP64,
                                         "launch": cfg2, "finite": ok2}
         extras["eval_n16_d2_hbm_1M_points_double"] = hbm_extra(ph, torch, max(3, args.steps // 4))
+        log("hbm-bound eval done")
         extras["eval_pcie_inclusive_host_buffers"] = pcie_extra(ph, torch, S, sysm, L, npts, gamma)
         extras["unfused_three_kernel_ablation"] = unfused_extra(ph, torch, S, sysm, gamma, 5)
+        log("unfused ablation done")
         extras.update(tracking_extras(ph, torch, cpu=not args.no_cpu_baseline))
+        log("tracking workloads done")
         extras["track_batch64_dd_mixed"] = batch_extra(ph, torch, cpu=not args.no_cpu_baseline)
+        log("batch done")
         if not args.no_cpu_baseline:
             extras["paper_shaped_eval"] = paper_shaped_extra(ph, torch)
         result["extras"] = extras
