@@ -276,6 +276,32 @@ int ph_track(const ph_system *target, const ph_system *start, const double gamma
              ph_track_report *rep, void *stream);
 
 /*
+ * ph_track_noalloc -- ph_track for callers that cannot allocate device memory
+ * (code that must not call hipMalloc: tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, results, synchrony and errors as
+ * ph_track, with these differences:
+ *   - the device scratch of a call (counters and work queue, the system
+ *     descriptor, the predictor history of predictor_order >= 2) lives in one
+ *     library-owned device buffer of 32 MiB per GPU, created when the library
+ *     is loaded on that GPU and held until the process ends; the call makes no
+ *     device allocation and frees nothing;
+ *   - opts->schedule must be PH_SCHED_PERSISTENT (PH_EUNSUPPORTED otherwise);
+ *   - an explicit start system must have been prepared for this target with
+ *     ph_eval_prepare (PH_EINVAL otherwise; it builds its term table);
+ *   - PH_EINVAL when the predictor history of the launch (3 * 2 * prec * 8
+ *     bytes per lane slot, 64 slots per workgroup, predictor_order >= 2 only)
+ *     exceeds the buffer's 32 MiB - 64 KiB: lower opts->blocks_per_cu.
+ * Every call on a GPU uses that GPU's one buffer, which keeps the previous
+ * call's contents (the call clears its counters itself): calls that overlap
+ * on one GPU (other threads, other streams) race and must be serialised by
+ * the caller.
+ */
+int ph_track_noalloc(const ph_system *target, const ph_system *start, const double gamma[2],
+                     int64_t npaths, const double *x_start, int64_t ld, const ph_track_opts *opts,
+                     double *x_end, int8_t *status, int8_t *reason, int32_t *steps,
+                     ph_track_report *rep, void *stream);
+
+/*
  * ph_track_batch -- many homotopies in one launch: the paths of nsys target
  * systems (total-degree start systems, roots-of-unity start points) are
  * concatenated into one device work queue; system s owns global path indices

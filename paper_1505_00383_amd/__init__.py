@@ -25,7 +25,8 @@ REASONS = {0: "NONE", 1: "SUCCESS", 2: "DIVERGED", 3: "STEP_UNDERFLOW", 4: "MAX_
 EXPORTED = ["ph_system_create", "ph_system_destroy", "ph_system_info", "ph_system_degrees",
             "ph_start_solutions", "ph_eval_jac", "ph_track_opts_default", "ph_last_error",
             "ph_arith_probe", "ph_track", "ph_track_batch", "ph_eval_set_config",
-            "ph_eval_autotune", "ph_track_autotune", "ph_eval_get_config", "ph_eval_prepare"]
+            "ph_eval_autotune", "ph_track_autotune", "ph_eval_get_config", "ph_eval_prepare",
+            "ph_track_noalloc"]
 
 # ph_eval_set_config kernels
 EVAL_AUTO, EVAL_GENERAL, EVAL_REGROW, EVAL_FAST, EVAL_FAST_VECROW, EVAL_UNFUSED = 0, 1, 2, 3, 4, 5
@@ -97,6 +98,7 @@ def load_library(path: str = LIB_PATH):
     L.ph_last_error.restype = ctypes.c_char_p
     L.ph_arith_probe.argtypes = [i32, i32, i64, P, P, P, P]
     L.ph_track.argtypes = [P, P, P, i64, P, i64, P, P, P, P, P, P, P]
+    L.ph_track_noalloc.argtypes = [P, P, P, i64, P, i64, P, P, P, P, P, P, P]
     L.ph_track_batch.argtypes = [i32, P, P, P, P, P, P, i64, P, P, P, P, P]
     L.ph_eval_set_config.argtypes = [P, P, i32, i32, i32, i32]
     L.ph_eval_prepare.argtypes = [P, P, i32, i64]
@@ -306,6 +308,18 @@ def track(sys: System, gamma, npaths: int, opts: TrackOpts | None = None, x_star
     """Track paths 0..npaths-1 of gamma(1-t) g + t f (ph_track).  x_start: device SoA
     start points [n*2*prec, ld] or None (roots of unity).  Returns a dict with
     device x_end [n*2*prec, ld] and numpy status / reason / steps, plus the report."""
+    return _track_one("ph_track", sys, gamma, npaths, opts, x_start, start, stream)
+
+
+def track_noalloc(sys: System, gamma, npaths: int, opts: TrackOpts | None = None, x_start=None,
+                  start: System | None = None, stream=None):
+    """track() through ph_track_noalloc: the library's fixed device scratch
+    instead of per-call allocations (persistent schedule only; an explicit
+    start system must be prepared with eval_prepare first)."""
+    return _track_one("ph_track_noalloc", sys, gamma, npaths, opts, x_start, start, stream)
+
+
+def _track_one(entry, sys, gamma, npaths, opts, x_start, start, stream):
     torch = _torch()
     opts = opts or track_opts()
     L = opts.prec
@@ -313,10 +327,10 @@ def track(sys: System, gamma, npaths: int, opts: TrackOpts | None = None, x_star
     x_end, status, reason, steps = _track_outputs(torch, sys.n_var * 2 * L, npaths, ld)
     rep = TrackReport()
     g = (ctypes.c_double * 2)(complex(gamma).real, complex(gamma).imag)
-    _check(load_library().ph_track(sys.handle, None if start is None else start.handle, g, npaths,
-                                   _ptr(x_start), ld, ctypes.byref(opts), _ptr(x_end),
-                                   _ptr(status), _ptr(reason), _ptr(steps), ctypes.byref(rep),
-                                   _stream(stream)))
+    fn = getattr(load_library(), entry)
+    _check(fn(sys.handle, None if start is None else start.handle, g, npaths, _ptr(x_start), ld,
+              ctypes.byref(opts), _ptr(x_end), _ptr(status), _ptr(reason), _ptr(steps),
+              ctypes.byref(rep), _stream(stream)))
     return dict(x_end=x_end, status=status[:npaths].cpu().numpy(),
                 reason=reason[:npaths].cpu().numpy(), steps=steps[:npaths].cpu().numpy(),
                 report=rep.as_dict())

@@ -64,6 +64,7 @@ int clear_counter_launch(unsigned int *c, hipStream_t st)
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 namespace ph {
@@ -113,11 +114,51 @@ struct DevBuf {
     }
 };
 
+// Device scratch of the entry point for callers that cannot allocate
+// (ph_track_noalloc): counters and work queues, the system descriptor and the
+// predictor history of one call live in this file-scope array, one copy per
+// GPU, held until the process ends.  Host code never passes the array's name
+// to a kernel or a copy (on the host it is only a stand-in symbol); it uses
+// the device address that hipGetSymbolAddress returns for the current device.
+constexpr size_t NOALLOC_BYTES = size_t(32) << 20;
+constexpr size_t NOALLOC_DESC_OFF = 4096;          // after the counters
+constexpr size_t NOALLOC_HIST_OFF = size_t(64) << 10;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+struct NoallocScratch {
+    void *ptr = nullptr;
+    bool done = false;
+};
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+static int noalloc_scratch_ptr(void **out)
+{
+    static std::mutex mu;
+    static NoallocScratch per_dev[64];
+    int dev = 0;
+    PH_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(PH_EUNSUPPORTED, "device index beyond 63");
+    std::lock_guard<std::mutex> lk(mu);
+    NoallocScratch &e = per_dev[dev];
+    if (!e.done) {
+        void *p = nullptr;
+        hipError_t er = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (er != hipSuccess || !p) return hip_fail(er, "hipGetSymbolAddress(scratch)");
+        e.ptr = p;
+        e.done = true;
+    }
+    *out = e.ptr;
+    return PH_OK;
+}
+
+// noalloc: device scratch for the no-allocation entry point (its address on
+// the current device), or NULL to allocate per call.
 static int track_impl(int nsys, const ph_system *const *targets, const ph_system *start,
                       const double *gammas, const int64_t *path_off, const int64_t *path_ids,
                       const double *x_start, int64_t ld, const ph_track_opts *opts, double *x_end,
                       int8_t *status, int8_t *reason, int32_t *steps, ph_track_report *rep,
-                      hipStream_t st)
+                      hipStream_t st, unsigned char *noalloc = nullptr)
 {
     auto t0 = std::chrono::steady_clock::now();
     if (!opts) return fail(PH_EINVAL, "null opts");
@@ -156,7 +197,7 @@ static int track_impl(int nsys, const ph_system *const *targets, const ph_system
             while (class_np[cls] < n || class_np[cls] < opts->lanes_per_path) ++cls;
             if (cls != c) continue;
             const DevTable *tab = nullptr;
-            rc = get_table(t, start, &tab);
+            rc = noalloc ? find_table(t, start, &tab) : get_table(t, start, &tab);
             if (rc) return rc;
             SysDesc d;
             std::memset(&d, 0, sizeof d);
@@ -212,6 +253,13 @@ static int track_impl(int nsys, const ph_system *const *targets, const ph_system
 
     // ---- device buffers: descriptors, path ids, counters, slot state
     DevBuf bdesc, bids, bctr, bstate, bhist;
+    if (noalloc) {
+        if (path_ids) return fail(PH_EUNSUPPORTED, "no-allocation tracking takes no path id list");
+        if (opts->schedule != PH_SCHED_PERSISTENT)
+            return fail(PH_EUNSUPPORTED, "no-allocation tracking runs the persistent schedule only");
+        if (sizeof(SysDesc) * desc.size() > NOALLOC_HIST_OFF - NOALLOC_DESC_OFF)
+            return fail(PH_EINVAL, "no-allocation tracking: too many systems for the scratch buffer");
+    }
     if (path_ids) {
         PH_HIP(hipMalloc(&bids.p, sizeof(int64_t) * total));
         PH_HIP(hipMemcpyAsync(bids.p, path_ids, sizeof(int64_t) * total, hipMemcpyHostToDevice, st));
@@ -220,13 +268,23 @@ static int track_impl(int nsys, const ph_system *const *targets, const ph_system
             d.path_ids = (const int64_t *)bids.p + path_off[s];
         }
     }
-    PH_HIP(hipMalloc(&bdesc.p, sizeof(SysDesc) * desc.size()));
-    PH_HIP(hipMemcpyAsync(bdesc.p, desc.data(), sizeof(SysDesc) * desc.size(), hipMemcpyHostToDevice, st));
-    PH_HIP(hipMalloc(&bctr.p, sizeof(unsigned long long) * 32));
-    PH_HIP(hipMemsetAsync(bctr.p, 0, sizeof(unsigned long long) * 32, st));
-    unsigned long long *ctr = (unsigned long long *)bctr.p;
+    void *desc_dev = nullptr;
+    unsigned long long *ctr = nullptr;
+    if (noalloc) {
+        desc_dev = noalloc + NOALLOC_DESC_OFF;
+        ctr = reinterpret_cast<unsigned long long *>(noalloc);
+    } else {
+        PH_HIP(hipMalloc(&bdesc.p, sizeof(SysDesc) * desc.size()));
+        PH_HIP(hipMalloc(&bctr.p, sizeof(unsigned long long) * 32));
+        desc_dev = bdesc.p;
+        ctr = (unsigned long long *)bctr.p;
+    }
+    PH_HIP(hipMemcpyAsync(desc_dev, desc.data(), sizeof(SysDesc) * desc.size(), hipMemcpyHostToDevice, st));
+    // counters, queues and the active count start at zero on every call (the
+    // no-allocation scratch keeps the previous call's contents)
+    PH_HIP(hipMemsetAsync(ctr, 0, sizeof(unsigned long long) * 32, st));
 
-    a.sys = (const SysDesc *)bdesc.p;
+    a.sys = (const SysDesc *)desc_dev;
     a.nsys = (int)desc.size();
     a.x_start = x_start;
     a.ld_start = ld;
@@ -267,8 +325,21 @@ static int track_impl(int nsys, const ph_system *const *targets, const ph_system
     if (opts->predictor_order > 1) {
         // three older points per lane slot, kept across launches
         a.hist_ld = (int64_t)blocks * 64;
-        PH_HIP(hipMalloc(&bhist.p, sizeof(double) * 3 * 2 * prec * (size_t)a.hist_ld));
-        a.hist = static_cast<double *>(bhist.p);
+        const size_t hist_bytes = sizeof(double) * 3 * 2 * prec * (size_t)a.hist_ld;
+        if (noalloc) {
+            if (hist_bytes > NOALLOC_BYTES - NOALLOC_HIST_OFF) {
+                char msg[200];
+                std::snprintf(msg, sizeof msg,
+                              "no-allocation tracking: the predictor history of %d workgroups needs %zu bytes, "
+                              "more than the %zu of the scratch buffer (lower blocks_per_cu)",
+                              blocks, hist_bytes, NOALLOC_BYTES - NOALLOC_HIST_OFF);
+                return fail(PH_EINVAL, msg);
+            }
+            a.hist = reinterpret_cast<double *>(noalloc + NOALLOC_HIST_OFF);
+        } else {
+            PH_HIP(hipMalloc(&bhist.p, hist_bytes));
+            a.hist = static_cast<double *>(bhist.p);
+        }
     }
 
     if (opts->schedule == PH_SCHED_GRAPH) {
@@ -377,6 +448,24 @@ extern "C" int ph_track(const ph_system *target, const ph_system *start, const d
     const int64_t off[2] = {0, npaths};
     return track_impl(1, &target, start, gamma, off, nullptr, x_start, ld, opts, x_end, status,
                       reason, steps, rep, (hipStream_t)stream);
+}
+
+extern "C" int ph_track_noalloc(const ph_system *target, const ph_system *start, const double gamma[2],
+                                int64_t npaths, const double *x_start, int64_t ld,
+                                const ph_track_opts *opts, double *x_end, int8_t *status,
+                                int8_t *reason, int32_t *steps, ph_track_report *rep, void *stream)
+{
+    if (!target || !gamma) return fail(PH_EINVAL, "null target or gamma");
+    if (npaths < 0) return fail(PH_EINVAL, "npaths < 0");
+    if (start && !x_start) return fail(PH_EINVAL, "a custom start system needs x_start");
+    if (start && (start->h.n_eq != target->h.n_eq || start->h.n_var != target->h.n_var))
+        return fail(PH_EINVAL, "start system shape differs from target");
+    void *scr = nullptr;
+    int rc = noalloc_scratch_ptr(&scr);
+    if (rc) return rc;
+    const int64_t off[2] = {0, npaths};
+    return track_impl(1, &target, start, gamma, off, nullptr, x_start, ld, opts, x_end, status,
+                      reason, steps, rep, (hipStream_t)stream, static_cast<unsigned char *>(scr));
 }
 
 extern "C" int ph_track_batch(int32_t nsys, const ph_system *const *targets, const double *gammas,
