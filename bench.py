@@ -693,10 +693,11 @@ def main():
     bpp = bytes_per_point(sysm, L)
     secs = ms * 1e-3
     achieved = fpp * npts / secs
-    kname = "eval_d_pinned_kernel" if L == 1 else f"eval_kernel<{L},8,true,true>"
+    fast = {1: "eval_d_pinned_kernel", 2: "eval_dd_arow_kernel"}
+    kname = fast.get(L, f"eval_kernel<{L},8,true,true>")
     kchoice = args.kernel or (tuned_cfg[0] if tuned_cfg else 0)
     if kchoice:
-        kname = {1: f"eval_kernel<{L},8,true,true>", 2: "eval_d_regrow_kernel<8>", 3: kname,
+        kname = {1: f"eval_kernel<{L},8,true,true>", 2: "eval_d_regrow_kernel<8>", 3: fast.get(L),
                  4: "eval_d_fast_kernel", 5: "coeff_kernel + mon_kernel + sum_kernel"}[kchoice]
     traffic = traffic_of(kname, tuned_cfg)
     result = {

@@ -673,7 +673,9 @@ int eval_launch(const DevTable &tab, const double gamma[2], int prec, int64_t np
     const bool wj = jac != nullptr;
     // which kernel: the fast path when its records exist, else the register
     // row in double, else the general kernel
-    const bool can_fast = prec == 1 && wj && tab.n_var <= 32 && tab.dfast;
+    // fast path: double (register row) or double double (row in the
+    // accumulation registers)
+    const bool can_fast = wj && tab.n_var <= 32 && tab.dfast && (prec == 1 || (prec == 2 && tab.mfast));
     const bool can_reg = prec == 1 && wj && tab.n_var <= 32 && tab.kmax <= 16;
     int kernel = cfg ? cfg->kernel : 0;
     if (kernel == 5) return unfused_launch(tab, gamma, prec, npts, t, x, ld, val, jac, st);
@@ -682,8 +684,15 @@ int eval_launch(const DevTable &tab, const double gamma[2], int prec, int64_t np
     if (!wj && kernel >= 2) kernel = 1;
     if ((kernel == 3 || kernel == 4) && !can_fast)
         return fail(PH_EUNSUPPORTED, "fast path not available for this system");
+    if (kernel == 4 && prec != 1)
+        return fail(PH_EUNSUPPORTED, "the compiler-held row is a complex-double kernel");
     if (kernel == 2 && !can_reg) return fail(PH_EUNSUPPORTED, "register-row kernel not available");
     if (kernel == 0) kernel = can_fast ? 3 : (can_reg ? 2 : 1);
+    if (kernel == 3 && prec == 2)
+        return dd_fast_launch(tab, gamma, npts, t, x, ld, val, jac, cfg && cfg->W > 0 ? cfg->W : 4,
+                              cfg && cfg->G > 0 ? cfg->G : 1, st);
+    if ((kernel == 3 || kernel == 4) && prec != 1)
+        return fail(PH_EUNSUPPORTED, "fast path not available at this precision");
     // waves per workgroup: all of them share the 64 points staged in LDS and
     // take their own equations; wide precisions want more waves per
     // workgroup because their LDS tile (n * L KB) limits workgroups per CU

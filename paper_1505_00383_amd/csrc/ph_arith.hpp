@@ -234,6 +234,72 @@ PH_HD R<L> r_mul_d(R<L> a, double b)
     }
 }
 
+// a * b + c * d in quad double with one renormalisation (the complex
+// product's components): the partial products of both pairs are grouped by
+// order of magnitude as in r_mul<4>, the levels 0..2 are summed with TwoSum
+// chains whose errors flow one level down, level 3 (products of order eps^3
+// and the level-2 errors) is summed in plain FP64, and the result is
+// renormalised once with TwoSum in both passes (a * b + c * d may cancel).
+// Error a few 2^-210 times |a b| + |c d|.
+PH_HD R<4> qd_dot2(const R<4> &a, const R<4> &b, const R<4> &c, const R<4> &d)
+{
+    // level 0
+    double p0, e00, r0, f00, s0, t0;
+    two_prod(a.v[0], b.v[0], p0, e00);
+    two_prod(c.v[0], d.v[0], r0, f00);
+    two_sum(p0, r0, s0, t0);
+    // level 1: a0 b1, a1 b0, c0 d1, c1 d0, the two level-0 product errors, t0
+    double p1a, e01, p1b, e10, r1a, f01, r1b, f10;
+    two_prod(a.v[0], b.v[1], p1a, e01);
+    two_prod(a.v[1], b.v[0], p1b, e10);
+    two_prod(c.v[0], d.v[1], r1a, f01);
+    two_prod(c.v[1], d.v[0], r1b, f10);
+    double s1, u1, u2, u3, u4, u5, u6;
+    two_sum(p1a, p1b, s1, u1);
+    two_sum(s1, r1a, s1, u2);
+    two_sum(s1, r1b, s1, u3);
+    two_sum(s1, e00, s1, u4);
+    two_sum(s1, f00, s1, u5);
+    two_sum(s1, t0, s1, u6);
+    // level 2: the six products of order eps^2 and the level-1 errors
+    double p2a, e02, p2b, e11, p2c, e20, r2a, f02, r2b, f11, r2c, f20;
+    two_prod(a.v[0], b.v[2], p2a, e02);
+    two_prod(a.v[1], b.v[1], p2b, e11);
+    two_prod(a.v[2], b.v[0], p2c, e20);
+    two_prod(c.v[0], d.v[2], r2a, f02);
+    two_prod(c.v[1], d.v[1], r2b, f11);
+    two_prod(c.v[2], d.v[0], r2c, f20);
+    double s2, w[15];
+    two_sum(p2a, p2b, s2, w[0]);
+    two_sum(s2, p2c, s2, w[1]);
+    two_sum(s2, r2a, s2, w[2]);
+    two_sum(s2, r2b, s2, w[3]);
+    two_sum(s2, r2c, s2, w[4]);
+    two_sum(s2, e01, s2, w[5]);
+    two_sum(s2, e10, s2, w[6]);
+    two_sum(s2, f01, s2, w[7]);
+    two_sum(s2, f10, s2, w[8]);
+    two_sum(s2, u1, s2, w[9]);
+    two_sum(s2, u2, s2, w[10]);
+    two_sum(s2, u3, s2, w[11]);
+    two_sum(s2, u4, s2, w[12]);
+    two_sum(s2, u5, s2, w[13]);
+    two_sum(s2, u6, s2, w[14]);
+    // level 3: products of order eps^3 (rounded), the level-2 product
+    // errors and the level-2 sum errors
+    double s3 = __builtin_fma(a.v[0], b.v[3], a.v[1] * b.v[2]);
+    s3 = __builtin_fma(a.v[2], b.v[1], s3);
+    s3 = __builtin_fma(a.v[3], b.v[0], s3);
+    s3 = __builtin_fma(c.v[0], d.v[3], s3);
+    s3 = __builtin_fma(c.v[1], d.v[2], s3);
+    s3 = __builtin_fma(c.v[2], d.v[1], s3);
+    s3 = __builtin_fma(c.v[3], d.v[0], s3);
+    s3 += ((e02 + e11) + (e20 + f02)) + ((f11 + f20) + (w[0] + w[1]));
+    s3 += ((w[2] + w[3]) + (w[4] + w[5])) + ((w[6] + w[7]) + (w[8] + w[9]));
+    s3 += ((w[10] + w[11]) + (w[12] + w[13])) + w[14];
+    return qd_renorm_safe(s0, s1, s2, s3, 0.0);
+}
+
 // ---------------------------------------------------------------------------
 // L-limb complex numbers
 // ---------------------------------------------------------------------------
@@ -269,8 +335,8 @@ PH_HD C<L> c_sub(C<L> a, C<L> b)
 // Complex product.  Double: four FMA-style operations.  Double double: each
 // component a*b - c*d is formed from the two leading exact products (TwoProd)
 // combined by one TwoSum, the four cross terms and the two product errors
-// folded into the error term, then one FastTwoSum.  Quad double: four
-// products and two sums.
+// folded into the error term, then one FastTwoSum.  Quad double: each
+// component a*b +- c*d by qd_dot2 (one renormalisation per component).
 template <int L>
 PH_HD C<L> c_mul(C<L> a, C<L> b)
 {
@@ -306,9 +372,7 @@ PH_HD C<L> c_mul(C<L> a, C<L> b)
         }
         return r;
     } else {
-        R<4> rr = r_mul<4>(a.re, b.re), ii = r_mul<4>(a.im, b.im);
-        R<4> ri = r_mul<4>(a.re, b.im), ir = r_mul<4>(a.im, b.re);
-        return C<4>{r_sub<4>(rr, ii), r_add<4>(ri, ir)};
+        return C<4>{qd_dot2(a.re, b.re, r_neg<4>(a.im), b.im), qd_dot2(a.re, b.im, a.im, b.re)};
     }
 }
 

@@ -136,18 +136,33 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
     if (emax > 4) dfast = false;
     const int planes = std::max(1, std::min(emax, 4) - 1);  // x, x^2, x^3 as needed
     std::vector<DTerm> dterm;
+    std::vector<MTerm> mterm;
     std::vector<int32_t> d_eq_off(ne + 1, 0), d_deg(ne, 0), d_run(1, 0);
+    // the double-double staging layout must fit the 160 KB of LDS: planes of
+    // 4 nv rows and a ones row, 512 bytes per row
+    const bool mfast = dfast && (size_t(planes) * nv * 4 + 4) * 512 <= 160 * 1024;
     if (dfast) {
         // LDS layout per workgroup (doubles, 64 lanes): plane p (x^(p+1)) of
         // variable v, component c at ((p * nv + v) * 2 + c) * 64; then a row
-        // of ones (re) and zeros (im)
+        // of ones (re) and zeros (im).  Double double: rows
+        // ((p * nv + v) * 4 + 2 c + limb) * 64, then the ones row {1, 0, 0, 0}.
         const uint32_t ones_off = uint32_t(planes * nv * 2 * 64 * 8);
+        const uint32_t ones_off2 = uint32_t(planes * nv * 4 * 64 * 8);
+        struct Rec {
+            DTerm d;
+            MTerm m;
+        };
+        std::vector<Rec> eqrec;
         auto emit_d = [&](const HostSystem &sy, int i, int sel) {
             for (int t = sy.eq_term_off[i]; t < sy.eq_term_off[i + 1]; ++t) {
-                DTerm r;
+                Rec rr;
+                DTerm &r = rr.d;
+                MTerm &m = rr.m;
                 std::memset(&r, 0, sizeof r);
+                std::memset(&m, 0, sizeof m);
                 r.cre = sy.coef[size_t(t) * 8];
                 r.cim = sy.coef[size_t(t) * 8 + 4];
+                for (int l = 0; l < 8; ++l) m.c[l] = sy.coef[size_t(t) * 8 + l];
                 int a = sy.term_fac_off[t], b = sy.term_fac_off[t + 1];
                 r.k = b - a;
                 // factors by exponent, largest first: the kernel multiplies
@@ -165,24 +180,35 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
                     r.po[l] = poff;
                     r.j2[l] = uint32_t(2 * v);
                     r.a[l] = double(e);
+                    m.xo[l] = uint32_t(v) * 4u * 64u * 8u;
+                    m.po[l] = e == 1 ? ones_off2 : uint32_t(((e - 2) * nv + v) * 4 * 64 * 8);
+                    m.jo[l] = uint32_t(8 * v);
+                    m.a[l] = double(e);
                     m3 += e >= 3;
                     m2 += e >= 2;
                 }
                 r.sel = sel | (m3 << 8) | (m2 << 16);
-                dterm.push_back(r);
+                m.k = r.k;
+                m.sel = r.sel;
+                eqrec.push_back(rr);
             }
         };
         d_run.assign(size_t(ne) * DRUN, 0);
         for (int i = 0; i < ne; ++i) {
-            const size_t first = dterm.size();
+            eqrec.clear();
             emit_d(f, i, 0);
             if (g) emit_d(*g, i, 1);
             // group the equation's terms by (k, number of factors with
             // a >= 2) so the kernel runs one straight-line loop per group
             // (a stable sort keeps the term order within a group)
             auto grp = [](const DTerm &x) { return drun_group(x.k, (x.sel >> 16) & 15); };
-            std::stable_sort(dterm.begin() + first, dterm.end(),
-                             [&](const DTerm &x, const DTerm &y) { return grp(x) < grp(y); });
+            std::stable_sort(eqrec.begin(), eqrec.end(),
+                             [&](const Rec &x, const Rec &y) { return grp(x.d) < grp(y.d); });
+            const size_t first = dterm.size();
+            for (const Rec &rr : eqrec) {
+                dterm.push_back(rr.d);
+                mterm.push_back(rr.m);
+            }
             for (int gg = 0; gg < DRUN; ++gg) {
                 size_t pos = first;
                 while (pos < dterm.size() && grp(dterm[pos]) < gg) ++pos;
@@ -191,8 +217,12 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
             d_eq_off[i + 1] = int32_t(dterm.size());
             d_deg[i] = (!g && ne == nv) ? f.deg[i] : 0;
         }
-        if (dterm.empty()) dterm.push_back(DTerm{});
+        if (dterm.empty()) {
+            dterm.push_back(DTerm{});
+            mterm.push_back(MTerm{});
+        }
     }
+    if (mterm.empty()) mterm.push_back(MTerm{});
 
     // ---- the unfused design: one slot per term value and per partial,
     // and for every output entry the list of slots summed into it ----
@@ -235,7 +265,8 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
     size_t o_zc = o_zo + align256(zc_off.size() * 4);
     size_t o_deo = o_zc + align256(zc.size() * 4);
     size_t o_dt = o_deo + align256(d_eq_off.size() * 4);
-    size_t o_dd = o_dt + align256(dterm.size() * sizeof(DTerm));
+    size_t o_mt = o_dt + align256(dterm.size() * sizeof(DTerm));
+    size_t o_dd = o_mt + align256(mterm.size() * sizeof(MTerm));
     size_t o_dr = o_dd + align256(d_deg.size() * 4);
     size_t o_us = o_dr + align256(d_run.size() * 4);
     size_t o_uo = o_us + align256(u_slot.size() * 4);
@@ -250,6 +281,7 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
     std::memcpy(host.data() + o_zc, zc.data(), zc.size() * 4);
     std::memcpy(host.data() + o_deo, d_eq_off.data(), d_eq_off.size() * 4);
     if (!dterm.empty()) std::memcpy(host.data() + o_dt, dterm.data(), dterm.size() * sizeof(DTerm));
+    std::memcpy(host.data() + o_mt, mterm.data(), mterm.size() * sizeof(MTerm));
     std::memcpy(host.data() + o_dd, d_deg.data(), d_deg.size() * 4);
     std::memcpy(host.data() + o_dr, d_run.data(), d_run.size() * 4);
     std::memcpy(host.data() + o_us, u_slot.data(), u_slot.size() * 4);
@@ -279,6 +311,8 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
     out.dfast_planes = planes;
     out.d_eq_off = reinterpret_cast<int32_t *>(dev + o_deo);
     out.dterm = reinterpret_cast<DTerm *>(dev + o_dt);
+    out.mfast = mfast;
+    out.mterm = reinterpret_cast<MTerm *>(dev + o_mt);
     out.d_deg = reinterpret_cast<int32_t *>(dev + o_dd);
     out.d_run = reinterpret_cast<int32_t *>(dev + o_dr);
     out.u_slot = reinterpret_cast<int32_t *>(dev + o_us);

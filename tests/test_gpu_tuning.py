@@ -44,7 +44,7 @@ def test_every_configuration_matches_oracle(L):
     ov, oj, sv, sj = oracle.eval_homotopy(s, L, x, t, g)
     S = ph.System(s)
     kernels = [ph.EVAL_GENERAL, ph.EVAL_UNFUSED] + ([ph.EVAL_REGROW, ph.EVAL_FAST, ph.EVAL_FAST_VECROW]
-                                                   if L == 1 else [])
+                                                   if L == 1 else ([ph.EVAL_FAST] if L == 2 else []))
     worst = 0.0
     ph.eval_prepare(S, L, unfused_points=npts)
     for k in kernels:
@@ -93,9 +93,13 @@ def test_inapplicable_kernel_is_refused():
     S = ph.System(s)
     rng = np.random.default_rng(12)
     x = synth.random_points(s.n_var, 70, 2, rng)
-    ph.eval_set_config(S, 2, ph.EVAL_FAST)            # double only
+    ph.eval_set_config(S, 2, ph.EVAL_FAST_VECROW)     # double only
     with pytest.raises(ph.PHError, match="-4"):
         _eval(S, s, 2, x, rng.uniform(0, 1, 70), 1.0)
+    x4 = synth.random_points(s.n_var, 70, 4, rng)
+    ph.eval_set_config(S, 4, ph.EVAL_FAST)            # double and double double only
+    with pytest.raises(ph.PHError, match="-4"):
+        _eval(S, s, 4, x4, rng.uniform(0, 1, 70), 1.0)
     with pytest.raises(ph.PHError):
         ph.eval_set_config(S, 1, 7)
 
@@ -138,7 +142,7 @@ def test_full_workload_every_launch_the_autotuner_may_pick(L):
                 assert e <= TOL[L], (k, W, G, e)
                 checked += 1
     ph.eval_set_config(S, L)
-    assert checked >= 18 * (3 if L == 1 else 1)    # 18 tilings per applicable kernel
+    assert checked >= 18 * {1: 3, 2: 2, 4: 1}[L]    # 18 tilings per applicable kernel
     print(f"[gpu] L={L} full workload, {checked} launch configurations match the oracle", flush=True)
 
 
@@ -183,8 +187,8 @@ def test_autotune_choice_persists_in_cache_file(tmp_path, monkeypatch):
     import torch as _t
     ph.eval_autotune(S3, ph.to_soa(x3), 64, 2, _t.as_tensor(t3, dtype=_t.float64).cuda(), g)
     last = cache.read_text().strip().split("\n")[-1].split()
-    assert int(last[3]) == 2 and int(last[4]) == 1      # only the general kernel runs DD
-    last[4] = "3"
+    assert int(last[3]) == 2 and int(last[4]) in (1, 3)  # general kernel or DD fast path
+    last[4] = "4"                                         # a double-only kernel
     cache.write_text(" ".join(last) + "\n")
     with pytest.raises(ph.PHError, match="-4"):
         _eval(ph.System(s3), s3, 2, x3, t3, g)

@@ -1,6 +1,8 @@
 """The double fast-path kernels keep the Jacobian row in registers that the
 compiler is told it may not use (a register budget plus clobbers on every
-statement that touches them).  Compile the evaluation source to gfx950
+statement that touches them); the double-double fast path keeps it in the 256
+accumulation registers (AGPRs), clobbered by every statement that touches
+them.  Compile the evaluation source to gfx950
 assembly and check that no compiler-generated instruction touches the
 pinned registers, that nothing spills to scratch, and that the kernel
 descriptor reserves the pinned registers.  The GPR indexing mode those
@@ -20,17 +22,26 @@ KERNELS = [(r"_ZN2ph20eval_d_pinned_kernel\S*", 128, "256"),
            (r"_ZN2ph22eval_d_pinned16_kernel\S*", 64, "128")]
 
 
-@pytest.fixture(scope="module")
-def asm(tmp_path_factory):
+def _compile(tmp_path_factory, src):
     if not os.path.exists(HIPCC):
         pytest.skip("hipcc not available")
     from paper_1505_00383_amd import build as B
-    out = tmp_path_factory.mktemp("asm") / "eval.s"
+    out = tmp_path_factory.mktemp("asm") / (src + ".s")
     cmd = [HIPCC, "-x", "hip"] + B.COMMON + B.DEVICE + [
-        "-S", "--cuda-device-only", os.path.join(B.CSRC, "eval.hip"), "-o", str(out)]
+        "-S", "--cuda-device-only", os.path.join(B.CSRC, src), "-o", str(out)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-2000:]
     return out.read_text()
+
+
+@pytest.fixture(scope="module")
+def asm(tmp_path_factory):
+    return _compile(tmp_path_factory, "eval.hip")
+
+
+@pytest.fixture(scope="module")
+def asm_dd(tmp_path_factory):
+    return _compile(tmp_path_factory, "eval_dd.hip")
 
 
 @pytest.mark.parametrize("pattern,first_pinned,vgprs", KERNELS)
@@ -49,3 +60,33 @@ def test_pinned_registers_untouched_by_compiler(asm, pattern, first_pinned, vgpr
     assert not m0, m0[:5]
     assert re.search(r"; ScratchSize: (\S+)", tail).group(1) == "0"
     assert re.search(r"; NumVgprs: (\S+)", tail).group(1) == vgprs
+
+
+def test_dd_row_accumulation_registers_untouched_by_compiler(asm_dd):
+    """eval_dd_arow_kernel: every instruction that names an accumulation
+    register sits in an inline-asm block, no compiler instruction uses M0, no
+    scratch, 256 AGPRs reserved and one wave per SIMD."""
+    name = re.search(r"^(_ZN2ph19eval_dd_arow_kernel\S*):", asm_dd, re.M).group(1)
+    start = asm_dd.index(name + ":")
+    end = asm_dd.index("; -- End function", start)
+    body = asm_dd[start:end]
+    tail = asm_dd[end:end + 3000]
+    outside = re.sub(r";;#ASMSTART.*?;;#ASMEND", "", body, flags=re.S)
+    code = [ln for ln in outside.split("\n") if ln.startswith("\t") and not ln.startswith("\t.")
+            and not ln.strip().startswith(";")]
+    bad = [ln for ln in code if re.search(r"\ba\[?\d", ln) or "accvgpr" in ln]
+    assert not bad, bad[:5]
+    m0 = [ln for ln in code if re.search(r"\bm0\b", ln)]
+    assert not m0, m0[:5]
+    assert re.search(r"; ScratchSize: (\S+)", tail).group(1) == "0"
+    assert re.search(r"; Occupancy: (\S+)", tail).group(1) == "1"
+    # the kernel's metadata entry: 256 AGPRs next to its name
+    meta = asm_dd[asm_dd.index(".amdgpu_metadata"):]
+    entry = meta[:meta.index(".name:           " + name)]
+    entry = entry[entry.rindex("- .agpr_count"):]
+    assert re.search(r"\.agpr_count:\s+(\d+)", entry).group(1) == "256"
+    # every indexed accumulation-register access is bracketed by the index mode
+    blocks = re.findall(r";;#ASMSTART(.*?);;#ASMEND", body, flags=re.S)
+    for b in blocks:
+        if "accvgpr" in b and "s_set_gpr_idx_on" in b:
+            assert b.strip().split("\n")[-1].strip() == "s_set_gpr_idx_off", b[-200:]
