@@ -616,6 +616,11 @@ def profile_mode(ph, torch, mode):
     if mode == "eval_hbm":
         print(json.dumps({"mode": mode, **hbm_extra(ph, torch, 20)}))
         return
+    if mode == "track_n8_dd":
+        s = synth.tracking_cubic()
+        res = ph.track(ph.System(s), synth.gamma_of(s), 6561, ph.track_opts(prec=2, mixed=1))
+        print(json.dumps({"mode": mode, "report": res["report"]}))
+        return
     if mode == "track_n16_qd":
         s = synth.tracking_quadratic16()
         res = ph.track(ph.System(s), synth.gamma_of(s), 2 ** 16, ph.track_opts(prec=4, mixed=1))
@@ -641,9 +646,11 @@ def main():
     ap.add_argument("--kernel", type=int, default=0,
                     help="evaluation kernel choice of ph_eval_set_config for the timed launches "
                          "(0 automatic; 5 the unfused three-kernel design)")
-    ap.add_argument("--mode", default="eval", choices=["eval", "eval_hbm", "track_n16_qd", "track_batch", "copy"],
+    ap.add_argument("--mode", default="eval",
+                    choices=["eval", "eval_hbm", "track_n8_dd", "track_n16_qd", "track_batch", "copy"],
                     help="eval: the benchmark line; the others run one workload for profiling: "
-                         "the HBM-bound n = 16 evaluation at 2^20 points, the 65536-path QD-mixed "
+                         "the HBM-bound n = 16 evaluation at 2^20 points, the 6561-path DD-mixed "
+                         "tracking of the n = 8 cubic system, the 65536-path QD-mixed "
                          "tracking, the 64-system batch, or a device copy of 2 GiB (calibrates "
                          "the HBM byte counters)")
     args = ap.parse_args()
@@ -693,7 +700,7 @@ def main():
     bpp = bytes_per_point(sysm, L)
     secs = ms * 1e-3
     achieved = fpp * npts / secs
-    fast = {1: "eval_d_pinned_kernel", 2: "eval_dd_arow_kernel"}
+    fast = {1: "eval_d_pinned_kernel", 2: "eval_dd_arow_kernel", 4: "eval_qd_arow_kernel"}
     kname = fast.get(L, f"eval_kernel<{L},8,true,true>")
     kchoice = args.kernel or (tuned_cfg[0] if tuned_cfg else 0)
     if kchoice:

@@ -219,9 +219,13 @@ int ph_eval_autotune(ph_system *target, const ph_system *start, const double gam
  *   rounds_per_launch   graph schedule: tracker rounds per kernel launch (32)
  *   launches_per_sync   graph schedule: graph replays between reads of the count (8)
  *   blocks_per_cu   workgroups per CU (0: the library's default, 8)
- *   lanes_per_path  lanes that share one path (0: the next power of two >= n;
- *                   4, 8, 16 or 32 to give each path more lanes than it
- *                   has unknowns, which spreads few paths over more waves)
+ *   lanes_per_path  lanes that share one path: 4, 8, 16 or 32; 0 selects
+ *                   the natural count (the next power of two >= n, at least
+ *                   4), doubled when the paths at their natural count would
+ *                   fill less than one wave per SIMD.  With 2 or 4 times the
+ *                   natural count, 2 or 4 lanes share each equation's term
+ *                   sweeps (results unchanged bit for bit), which spreads few
+ *                   paths over more waves
  */
 #define PH_SCHED_PERSISTENT 0
 #define PH_SCHED_GRAPH 1

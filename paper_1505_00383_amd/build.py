@@ -28,6 +28,38 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
           "-munsafe-fp-atomics"]
 
 
+# Sources whose compiled gfx950 assembly tests/test_pinned_registers.py
+# inspects: the build keeps it (-save-temps) with a fingerprint of what it was
+# compiled from, so the check need not compile them a second time.
+ASM_KEPT = ("eval.hip", "eval_dd.hip", "eval_qd.hip")
+
+
+def asm_fingerprint(src: str) -> str:
+    """sha256 of the source, every header beside it and the flags."""
+    import hashlib
+    h = hashlib.sha256()
+    names = [src] + sorted(f for f in os.listdir(CSRC) if f.endswith(".hpp"))
+    for f in names:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    h.update(" ".join(COMMON + DEVICE).encode())
+    return h.hexdigest()
+
+
+def kept_asm(src: str) -> str | None:
+    """Path of the device assembly the last build kept for src, if it was
+    compiled from the current sources, else None."""
+    stem = src.rsplit(".", 1)[0]
+    path = os.path.join(BUILD, f"{stem}-hip-amdgcn-amd-amdhsa-{ARCH}.s")
+    fp = os.path.join(BUILD, src + ".asm.sha256")
+    if not (os.path.exists(path) and os.path.exists(fp)):
+        return None
+    with open(fp) as fh:
+        if fh.read().strip() != asm_fingerprint(src):
+            return None
+    return path
+
+
 # track_unit.hip holds the tracker launchers for one (residual limbs, FP64
 # solves) pair per compilation: six objects built in parallel.
 TRACK_UNIT = "track_unit.hip"
@@ -54,10 +86,15 @@ def _compile(job) -> str:
     src, oname, extra = job
     obj = os.path.join(BUILD, oname)
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC] + lang + COMMON + DEVICE + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
-    r = subprocess.run(cmd, capture_output=True, text=True)
+    keep = ["-save-temps=obj"] if src in ASM_KEPT else []
+    fp = asm_fingerprint(src) if keep else None
+    cmd = [HIPCC] + lang + COMMON + DEVICE + extra + keep + ["-c", os.path.join(CSRC, src), "-o", obj]
+    r = subprocess.run(cmd, capture_output=True, text=True, cwd=BUILD)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
+    if keep:
+        with open(os.path.join(BUILD, src + ".asm.sha256"), "w") as fh:
+            fh.write(fp + "\n")
     return obj
 
 

@@ -106,7 +106,7 @@ __device__ __forceinline__ void jac_acc(double *__restrict__ jrow, int64_t ld, b
 }
 
 template <int L, int KMAX, bool XLDS, bool JAC>
-__global__ void __launch_bounds__(512) eval_kernel(EvalArgs a)
+__device__ __forceinline__ void eval_body(const EvalArgs &a)
 {
     extern __shared__ double xl[];
     const int lane = threadIdx.x & 63;
@@ -187,6 +187,20 @@ __global__ void __launch_bounds__(512) eval_kernel(EvalArgs a)
             }
         }
     }
+}
+
+template <int L, int KMAX, bool XLDS, bool JAC>
+__global__ void __launch_bounds__(512) eval_kernel(EvalArgs a)
+{
+    eval_body<L, KMAX, XLDS, JAC>(a);
+}
+
+// The same at one wave per SIMD (at most four waves per workgroup): the
+// quad-double sweep then has 512 registers and spills nothing to scratch.
+template <int L, int KMAX, bool XLDS, bool JAC>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) eval_kernel_w1(EvalArgs a)
+{
+    eval_body<L, KMAX, XLDS, JAC>(a);
 }
 
 // H and J leave a register-row kernel exactly once and are not read again by
@@ -623,7 +637,10 @@ template <int L, int KMAX, bool XLDS, bool JAC>
 static int launch4(const EvalArgs &a, int W, int G, size_t lds, hipStream_t st)
 {
     dim3 grid((unsigned)((a.npts + 63) / 64), (unsigned)G);
-    hipLaunchKernelGGL((eval_kernel<L, KMAX, XLDS, JAC>), grid, dim3(64 * W), XLDS ? lds : 0, st, a);
+    if (L == 4 && W <= 4)
+        hipLaunchKernelGGL((eval_kernel_w1<L, KMAX, XLDS, JAC>), grid, dim3(64 * W), XLDS ? lds : 0, st, a);
+    else
+        hipLaunchKernelGGL((eval_kernel<L, KMAX, XLDS, JAC>), grid, dim3(64 * W), XLDS ? lds : 0, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "eval_kernel launch");
     return PH_OK;
@@ -673,9 +690,9 @@ int eval_launch(const DevTable &tab, const double gamma[2], int prec, int64_t np
     const bool wj = jac != nullptr;
     // which kernel: the fast path when its records exist, else the register
     // row in double, else the general kernel
-    // fast path: double (register row) or double double (row in the
-    // accumulation registers)
-    const bool can_fast = wj && tab.n_var <= 32 && tab.dfast && (prec == 1 || (prec == 2 && tab.mfast));
+    // fast path: double (register row), double double or quad double (row
+    // in the accumulation registers)
+    const bool can_fast = wj && tab.n_var <= 32 && tab.dfast && (prec == 1 || tab.mfast);
     const bool can_reg = prec == 1 && wj && tab.n_var <= 32 && tab.kmax <= 16;
     int kernel = cfg ? cfg->kernel : 0;
     if (kernel == 5) return unfused_launch(tab, gamma, prec, npts, t, x, ld, val, jac, st);
@@ -690,6 +707,9 @@ int eval_launch(const DevTable &tab, const double gamma[2], int prec, int64_t np
     if (kernel == 0) kernel = can_fast ? 3 : (can_reg ? 2 : 1);
     if (kernel == 3 && prec == 2)
         return dd_fast_launch(tab, gamma, npts, t, x, ld, val, jac, cfg && cfg->W > 0 ? cfg->W : 4,
+                              cfg && cfg->G > 0 ? cfg->G : 1, st);
+    if (kernel == 3 && prec == 4)
+        return qd_fast_launch(tab, gamma, npts, t, x, ld, val, jac, cfg && cfg->W > 0 ? cfg->W : 4,
                               cfg && cfg->G > 0 ? cfg->G : 1, st);
     if ((kernel == 3 || kernel == 4) && prec != 1)
         return fail(PH_EUNSUPPORTED, "fast path not available at this precision");

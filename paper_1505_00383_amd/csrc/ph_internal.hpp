@@ -59,12 +59,13 @@ struct DTerm {
     int32_t pad[2];
 };
 
-// Term record of the double-double fast path, in the same order as the DTerm
-// records (the same d_run groups index both): the coefficient in all its
-// limbs, per factor the LDS byte offsets of x_{j_l} and x_{j_l}^{a_l - 1} in
-// the double-double staging layout (plane, variable, {re hi, re lo, im hi,
-// im lo}, lane), the accumulation-register index 8 j_l of its Jacobian
-// column, and the exponent as a double.
+// Term record of the double-double and quad-double fast paths, in the same
+// order as the DTerm records (the same d_run groups index both): the
+// coefficient in all its limbs, per factor the LDS byte offsets of x_{j_l}
+// and x_{j_l}^{a_l - 1} (both staging layouts give a (plane, variable) block
+// 2048 bytes: DD four rows of 64 points, QD eight rows of 32 points), the
+// accumulation-register index 8 j_l of its Jacobian column, and the exponent
+// as a double.
 struct MTerm {
     double c[8];     // [re, im][4 limbs]
     int32_t k, sel;  // as in DTerm
@@ -84,8 +85,8 @@ struct DevTable {
     int32_t *d_eq_off = nullptr; // [n_eq + 1] offsets into dterm
     DTerm *dterm = nullptr;      // fast-path records (target terms, custom start terms)
     int32_t *d_deg = nullptr;    // [n_eq] total-degree start exponents (0: explicit start)
-    bool mfast = false;          // the double-double records below are valid (LDS fits)
-    MTerm *mterm = nullptr;      // double-double fast-path records, parallel to dterm
+    bool mfast = false;          // the DD / QD records below are valid (LDS fits)
+    MTerm *mterm = nullptr;      // DD / QD fast-path records, parallel to dterm
     int32_t *d_run = nullptr;    // [n_eq][DRUN]: records of equation i in group g (k
                                  // factors, m of them with a >= 2; g = drun_group(k, m))
                                  // are d_run[i*DRUN+g] .. d_run[i*DRUN+g+1]-1
@@ -109,7 +110,7 @@ struct DevTable {
 // Kernel choice and tiling of one evaluation: kernel 0 automatic, 1 general
 // (Jacobian row accumulated in the output), 2 register row (double, n <= 32),
 // 3 fast path with the row pinned in registers (double: upper architectural
-// registers; double double: accumulation registers), 4 the double fast path
+// registers; double double and quad double: accumulation registers), 4 the double fast path
 // with a compiler-held row, 5 the unfused coeff / mon / sum kernels; W waves
 // per workgroup, G equation groups (0: default).
 struct EvalCfg {
@@ -161,6 +162,11 @@ int unfused_launch(const DevTable &tab, const double gamma[2], int prec, int64_t
 // Double-double fast path (kernel choice 3 at prec 2): Jacobian row in the
 // accumulation registers, W <= 4 waves per workgroup, G equation groups.
 int dd_fast_launch(const DevTable &tab, const double gamma[2], int64_t npts, const double *t,
+                   const double *x, int64_t ld, double *val, double *jac, int W, int G,
+                   hipStream_t st);
+// Quad-double fast path (kernel choice 3 at prec 4): two lanes per point, each
+// lane's component of the Jacobian row in the accumulation registers.
+int qd_fast_launch(const DevTable &tab, const double gamma[2], int64_t npts, const double *t,
                    const double *x, int64_t ld, double *val, double *jac, int W, int G,
                    hipStream_t st);
 // Evaluation launch with an explicit configuration (cfg == NULL: defaults).

@@ -55,6 +55,10 @@ __device__ __forceinline__ double gmax_d(double v)
     }
 }
 
+// L-limb sum over the group.  A zero operand is skipped rather than added:
+// a multi-limb addition may renormalise the limbs of the other operand, and
+// the rows and lanes a group has beyond its system's unknowns (zeros) must
+// not change any bit of the result, whatever the lane count.
 template <int NP, int L, int O = 1>
 __device__ __forceinline__ R<L> gsum_r(R<L> v)
 {
@@ -62,7 +66,13 @@ __device__ __forceinline__ R<L> gsum_r(R<L> v)
         R<L> u;
 #pragma unroll
         for (int l = 0; l < L; ++l) u.v[l] = red_partner<O>(v.v[l]);
-        return gsum_r<NP, L, 2 * O>(r_add<L>(v, u));
+        R<L> s;
+        if constexpr (L == 1) {
+            s = r_add<L>(v, u);
+        } else {
+            s = u.v[0] == 0.0 ? v : (v.v[0] == 0.0 ? u : r_add<L>(v, u));
+        }
+        return gsum_r<NP, L, 2 * O>(s);
     } else {
         return v;
     }
@@ -372,7 +382,14 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
         const double tt = phase == PH_POLISH ? 1.0 : t1;
         const SysDesc &sd = a.sys[sidx];
 
-        // ---- evaluate H and J at (xh, tt): lane i does equation i ----------
+        // ---- evaluate H and J at (xh, tt) ----------------------------------
+        // sub = the smallest power of two >= n (at least 4); with nsh = NP / sub
+        // lanes per equation, lane i = sr * sub + eq works on equation eq: the
+        // nsh lanes of an equation take its terms round-robin (the term sweeps
+        // run side by side) and lane eq adds every contribution in term order,
+        // so the results do not depend on nsh.  A helper lane (sr > 0) hands its
+        // term's value and partials over in its own row of the matrix, which
+        // no equation uses (rows >= sub >= n), and clears the row afterwards.
 #pragma unroll
         for (int l = 0; l < L; ++l) {
             xg[i * 2 * L + l] = xh.re.v[l];
@@ -383,8 +400,15 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        int sub = 4;
+        while (sub < n) sub *= 2;
+        // a helper's row holds 2L + kmax 2LS doubles of hand-over
+        if (sub > NP || 2 * L + sd.kmax * 2 * LS > (NP + 1) * 2 * LS) sub = NP;
+        const int nsh = NP / sub, eq = i % sub, sr = i / sub;
+        // m-th double of row `row` of the group's matrix (hand-over slots)
+        auto slot = [&](int row, int m) -> double * { return W(m / (2 * LS), row) + m % (2 * LS); };
         C<L> v = c_zero<L>();
-        if (busy && i < n) {
+        if (busy && eq < n) {
             double o1, oe;
             two_sum(1.0, -tt, o1, oe);
             R<L> omt = r_zero<L>();
@@ -400,32 +424,94 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
                 }
                 return z;
             };
-            const int s0 = sd.eq_off[i], s1 = sd.eq_off[i + 1];
-            for (int s = s0; s < s1; ++s) {
-                const int4 d = sd.tdesc[s];
-                C<L> c;
+            auto add_part = [&](uint32_t w, const C<LS> &part) {
+                double *en = W(fac_var(w), eq);
+                lds_put<LS>(en, c_add<LS>(lds_get<LS>(en), part));
+            };
+            const int s0 = sd.eq_off[eq], s1 = sd.eq_off[eq + 1];
+            for (int sb = s0; sb < s1; sb += nsh) {
+                const int s = sb + sr;
+                if (s < s1) {
+                    const int4 d = sd.tdesc[s];
+                    C<L> c;
 #pragma unroll
-                for (int l = 0; l < L; ++l) {
-                    c.re.v[l] = sd.coef[(int64_t)s * 8 + l];
-                    c.im.v[l] = sd.coef[(int64_t)s * 8 + 4 + l];
-                }
-                c = d.z ? c_mul<L>(c, gs) : c_mul_d<L>(c, tt);
-                if (d.x == 0) {
-                    v = c_add<L>(v, c);
-                    continue;
-                }
-                uint32_t fw[KMAX];
+                    for (int l = 0; l < L; ++l) {
+                        c.re.v[l] = sd.coef[(int64_t)s * 8 + l];
+                        c.im.v[l] = sd.coef[(int64_t)s * 8 + 4 + l];
+                    }
+                    c = d.z ? c_mul<L>(c, gs) : c_mul_d<L>(c, tt);
+                    C<L> tv = c;
+                    if (d.x > 0) {
+                        uint32_t fw[KMAX];
 #pragma unroll
-                for (int l = 0; l < KMAX; ++l)
-                    if (l < d.x) fw[l] = sd.fac[d.y + l];
-                v = c_add<L>(v, term_sweep<KMAX, true, (L == 1)>(
-                                    d.x, fw, c, X, [&](int, uint32_t w, const C<L> &part) {
-                                        double *e = W(fac_var(w), i);
-                                        lds_put<LS>(e, c_add<LS>(lds_get<LS>(e), narrow<LS, L>(part)));
-                                    }));
+                        for (int l = 0; l < KMAX; ++l)
+                            if (l < d.x) fw[l] = sd.fac[d.y + l];
+                        tv = term_sweep<KMAX, true, (L == 1)>(
+                            d.x, fw, c, X, [&](int l, uint32_t w, const C<L> &part) {
+                                const C<LS> pn = narrow<LS, L>(part);
+                                if (sr == 0) {
+                                    add_part(w, pn);
+                                } else {
+#pragma unroll
+                                    for (int q = 0; q < LS; ++q) {
+                                        *slot(i, 2 * L + l * 2 * LS + q) = pn.re.v[q];
+                                        *slot(i, 2 * L + l * 2 * LS + LS + q) = pn.im.v[q];
+                                    }
+                                }
+                            });
+                    }
+                    if (sr == 0) {
+                        v = c_add<L>(v, tv);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < L; ++q) {
+                            *slot(i, q) = tv.re.v[q];
+                            *slot(i, L + q) = tv.im.v[q];
+                        }
+                    }
+                }
+                if (nsh > 1) {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                    if (sr == 0) {
+                        // the helpers' terms, in term order, partials in the
+                        // order the sweep issues them (last factor first)
+                        for (int q = 1; q < nsh && sb + q < s1; ++q) {
+                            const int hrow = i + q * sub;
+                            const int4 d = sd.tdesc[sb + q];
+                            for (int l = d.x - 1; l >= 0; --l) {
+                                C<LS> pn;
+#pragma unroll
+                                for (int z = 0; z < LS; ++z) {
+                                    pn.re.v[z] = *slot(hrow, 2 * L + l * 2 * LS + z);
+                                    pn.im.v[z] = *slot(hrow, 2 * L + l * 2 * LS + LS + z);
+                                }
+                                add_part(sd.fac[d.y + l], pn);
+                            }
+                            C<L> tv;
+#pragma unroll
+                            for (int z = 0; z < L; ++z) {
+                                tv.re.v[z] = *slot(hrow, z);
+                                tv.im.v[z] = *slot(hrow, L + z);
+                            }
+                            v = c_add<L>(v, tv);
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                }
             }
-            lds_put<LS>(W(NP, i), narrow<LS, L>(c_sub<L>(c_zero<L>(), v)));
+            if (sr == 0) lds_put<LS>(W(NP, i), narrow<LS, L>(c_sub<L>(c_zero<L>(), v)));
         }
+        if (nsh > 1 && sr > 0) {
+#pragma unroll
+            for (int j = 0; j <= NP; ++j) lds_put<LS>(W(j, i), c_zero<LS>());
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 
         // ---- correct: MGS least squares on [J | -H], row i in lane i ------
         // residual at the point where the Newton system is formed (the

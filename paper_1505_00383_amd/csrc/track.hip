@@ -175,6 +175,26 @@ static int track_impl(int nsys, const ph_system *const *targets, const ph_system
     if (ld < total) return fail(PH_EINVAL, "ld < number of paths");
     const int prec = opts->prec;
 
+    int dev = 0, cus = 256;
+    PH_HIP(hipGetDevice(&dev));
+    PH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    // lanes per path: as asked, else the natural count, doubled when the
+    // paths at their natural count fill less than one wave per SIMD (the
+    // extra lanes share each equation's term sweeps; results are unchanged)
+    int lanes_pp = opts->lanes_per_path;
+    if (lanes_pp == 0) {
+        double lanes = 0;
+        int nat_max = 4;
+        for (int s = 0; s < nsys; ++s) {
+            if (!targets[s]) return fail(PH_EINVAL, "null target system");
+            int nat = 4;
+            while (nat < targets[s]->h.n_var) nat *= 2;
+            nat_max = std::max(nat_max, nat);
+            lanes += (double)(path_off[s + 1] - path_off[s]) * nat;
+        }
+        if (lanes < 64.0 * 4 * cus && 2 * nat_max <= 32) lanes_pp = 2 * nat_max;
+    }
+
     // ---- systems grouped by lane-count class (4, 8, 16, 32 lanes per path)
     std::vector<SysDesc> desc;
     desc.reserve(nsys);
@@ -194,7 +214,7 @@ static int track_impl(int nsys, const ph_system *const *targets, const ph_system
             if (t->h.n_eq != n) return fail(PH_EUNSUPPORTED, "tracking needs square systems");
             if (n > 32) return fail(PH_EUNSUPPORTED, "tracking is limited to n <= 32");
             int cls = 0;
-            while (class_np[cls] < n || class_np[cls] < opts->lanes_per_path) ++cls;
+            while (class_np[cls] < n || class_np[cls] < lanes_pp) ++cls;
             if (cls != c) continue;
             const DevTable *tab = nullptr;
             rc = noalloc ? find_table(t, start, &tab) : get_table(t, start, &tab);
@@ -300,9 +320,6 @@ static int track_impl(int nsys, const ph_system *const *targets, const ph_system
     a.eps_sing = eps_singular(opts->mixed ? 1 : prec);
 
     // ---- blocks: per class proportional to its work, capped by residency
-    int dev = 0, cus = 256;
-    PH_HIP(hipGetDevice(&dev));
-    PH_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     int per_cu = opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 8;
     int cap = cus * per_cu;
     if (const char *env = std::getenv("PH_TRACK_BLOCKS")) {
@@ -553,12 +570,13 @@ extern "C" int ph_track_autotune(int32_t nsys, const ph_system *const *targets, 
     PH_HIP(hipMalloc(&bst.p, (size_t)ns));
 
     // candidates: residency-limited workgroups per CU, both schedules, the
-    // natural lane count and twice it (more waves for few paths)
+    // natural lane count and two or four times it (the extra lanes share each
+    // equation's term sweeps: more waves and shorter rounds for few paths)
     int np_max = 4;
     while (np_max < maxn) np_max *= 2;
     struct Cand { int sch, rnd, bpc, lanes; };
     std::vector<Cand> cands;
-    for (int lanes : {0, 2 * np_max}) {
+    for (int lanes : {0, 2 * np_max, 4 * np_max}) {
         if (lanes > 32) continue;
         const int lcap = (int)std::max<size_t>(
             1, (160 * 1024) / track_lds_bytes(opts->prec, opts->mixed, lanes ? lanes : np_max));

@@ -283,8 +283,8 @@ def _exp_system(seed, n, exps, terms=10, kmax=5):
     return synth.system_from_terms(n, eqs)
 
 
-# exponents 1..4 take the double and double-double fast paths (x^3 plane for
-# a = 4); 5, 8 and 64 fall back to the register-row and general kernels
+# exponents 1..4 take the fast paths of every precision (x^3 plane for a = 4);
+# 5, 8 and 64 fall back to the register-row and general kernels
 EXP_SETS = {"a<=4": (1, 2, 3, 4), "a=5,8,64": (1, 5, 8, 64)}
 
 
@@ -305,7 +305,7 @@ def test_eval_high_exponents_every_kernel_and_tiling(L, which):
     xs = ph.to_soa(x)
     tt = torch.as_tensor(t, dtype=torch.float64).cuda()
     kernels = [ph.EVAL_FAST, ph.EVAL_FAST_VECROW, ph.EVAL_REGROW, ph.EVAL_GENERAL] if L == 1 \
-        else ([ph.EVAL_FAST, ph.EVAL_GENERAL] if L == 2 else [ph.EVAL_GENERAL])
+        else [ph.EVAL_FAST, ph.EVAL_GENERAL]
     ran, worst = set(), 0.0
     for k in kernels:
         for W in (1, 2, 4, 6, 8):
@@ -330,8 +330,7 @@ def test_eval_high_exponents_every_kernel_and_tiling(L, which):
     print(f"[gpu] exponents {which} L={L}: kernels {sorted(ran)}, worst err/S={worst:.2e}", flush=True)
     if L == 1:
         assert ph.EVAL_REGROW in ran and ph.EVAL_GENERAL in ran
-    if L in (1, 2):
-        assert (ph.EVAL_FAST in ran) == (which == "a<=4")
+    assert (ph.EVAL_FAST in ran) == (which == "a<=4")
 
 
 def test_values_only_after_autotune():

@@ -351,17 +351,29 @@ def test_order4_graph_schedule_matches_persistent_bitwise():
 
 @pytest.mark.parametrize("lanes", [16, 32])
 def test_more_lanes_per_path_same_results(lanes):
-    """Giving each path more lanes than unknowns (idle rows and columns in
-    the group) changes nothing in the arithmetic: endpoints, status and step
-    counts are bitwise those of the natural lane count."""
+    """Giving each path two or four times its natural lane count (8 for
+    n = 8: the extra lanes share each equation's term sweeps and the first
+    lane of an equation adds the contributions in term order) changes nothing
+    in the arithmetic: endpoints, status and step counts are bitwise those of
+    the natural lane count, in double-double and quad-double residuals."""
     s = synth.tracking_cubic()
     g = synth.gamma_of(s)
     S = ph.System(s)
-    a = ph.track(S, g, 400, ph.track_opts(prec=2, mixed=1))
+    a = ph.track(S, g, 400, ph.track_opts(prec=2, mixed=1, lanes_per_path=8))
     b = ph.track(S, g, 400, ph.track_opts(prec=2, mixed=1, lanes_per_path=lanes))
     import torch
     assert (a["status"] == b["status"]).all() and (a["steps"] == b["steps"]).all()
     assert torch.equal(a["x_end"], b["x_end"])
+    # quad-double plain (the hand-over carries four limbs per partial)
+    paths = np.arange(0, 6561, 97)
+    x0 = ph.start_solutions(S, 4, 0, 6561)[:, torch.as_tensor(paths, device="cuda")].contiguous()
+    c = ph.track(S, g, len(paths), ph.track_opts(prec=4, mixed=0, lanes_per_path=8), x_start=x0)
+    d = ph.track(S, g, len(paths), ph.track_opts(prec=4, mixed=0, lanes_per_path=lanes), x_start=x0)
+    assert (c["status"] == d["status"]).all() and (c["steps"] == d["steps"]).all()
+    assert torch.equal(c["x_end"], d["x_end"])
+    # and the default on a few paths takes the doubled count: the same results
+    e = ph.track(S, g, 400, ph.track_opts(prec=2, mixed=1))
+    assert torch.equal(a["x_end"], e["x_end"]) and (a["steps"] == e["steps"]).all()
 
 
 def test_empty_inputs_and_empty_batch_member():

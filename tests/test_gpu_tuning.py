@@ -44,7 +44,7 @@ def test_every_configuration_matches_oracle(L):
     ov, oj, sv, sj = oracle.eval_homotopy(s, L, x, t, g)
     S = ph.System(s)
     kernels = [ph.EVAL_GENERAL, ph.EVAL_UNFUSED] + ([ph.EVAL_REGROW, ph.EVAL_FAST, ph.EVAL_FAST_VECROW]
-                                                   if L == 1 else ([ph.EVAL_FAST] if L == 2 else []))
+                                                   if L == 1 else [ph.EVAL_FAST])
     worst = 0.0
     ph.eval_prepare(S, L, unfused_points=npts)
     for k in kernels:
@@ -97,7 +97,7 @@ def test_inapplicable_kernel_is_refused():
     with pytest.raises(ph.PHError, match="-4"):
         _eval(S, s, 2, x, rng.uniform(0, 1, 70), 1.0)
     x4 = synth.random_points(s.n_var, 70, 4, rng)
-    ph.eval_set_config(S, 4, ph.EVAL_FAST)            # double and double double only
+    ph.eval_set_config(S, 4, ph.EVAL_REGROW)          # double only
     with pytest.raises(ph.PHError, match="-4"):
         _eval(S, s, 4, x4, rng.uniform(0, 1, 70), 1.0)
     with pytest.raises(ph.PHError):
@@ -142,7 +142,7 @@ def test_full_workload_every_launch_the_autotuner_may_pick(L):
                 assert e <= TOL[L], (k, W, G, e)
                 checked += 1
     ph.eval_set_config(S, L)
-    assert checked >= 18 * {1: 3, 2: 2, 4: 1}[L]    # 18 tilings per applicable kernel
+    assert checked >= 18 * {1: 3, 2: 2, 4: 2}[L]    # 18 tilings per applicable kernel
     print(f"[gpu] L={L} full workload, {checked} launch configurations match the oracle", flush=True)
 
 

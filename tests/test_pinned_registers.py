@@ -23,9 +23,13 @@ KERNELS = [(r"_ZN2ph20eval_d_pinned_kernel\S*", 128, "256"),
 
 
 def _compile(tmp_path_factory, src):
+    from paper_1505_00383_amd import build as B
+    kept = B.kept_asm(src)          # the assembly the build kept, if current
+    if kept:
+        with open(kept) as f:
+            return f.read()
     if not os.path.exists(HIPCC):
         pytest.skip("hipcc not available")
-    from paper_1505_00383_amd import build as B
     out = tmp_path_factory.mktemp("asm") / (src + ".s")
     cmd = [HIPCC, "-x", "hip"] + B.COMMON + B.DEVICE + [
         "-S", "--cuda-device-only", os.path.join(B.CSRC, src), "-o", str(out)]
@@ -39,9 +43,11 @@ def asm(tmp_path_factory):
     return _compile(tmp_path_factory, "eval.hip")
 
 
-@pytest.fixture(scope="module")
-def asm_dd(tmp_path_factory):
-    return _compile(tmp_path_factory, "eval_dd.hip")
+@pytest.fixture(scope="module", params=[("eval_dd.hip", "_ZN2ph19eval_dd_arow_kernel"),
+                                        ("eval_qd.hip", "_ZN2ph19eval_qd_arow_kernel")])
+def asm_acc(request, tmp_path_factory):
+    src, kernel = request.param
+    return _compile(tmp_path_factory, src), kernel
 
 
 @pytest.mark.parametrize("pattern,first_pinned,vgprs", KERNELS)
@@ -62,11 +68,12 @@ def test_pinned_registers_untouched_by_compiler(asm, pattern, first_pinned, vgpr
     assert re.search(r"; NumVgprs: (\S+)", tail).group(1) == vgprs
 
 
-def test_dd_row_accumulation_registers_untouched_by_compiler(asm_dd):
-    """eval_dd_arow_kernel: every instruction that names an accumulation
-    register sits in an inline-asm block, no compiler instruction uses M0, no
-    scratch, 256 AGPRs reserved and one wave per SIMD."""
-    name = re.search(r"^(_ZN2ph19eval_dd_arow_kernel\S*):", asm_dd, re.M).group(1)
+def test_accumulation_register_row_untouched_by_compiler(asm_acc):
+    """eval_dd_arow_kernel and eval_qd_arow_kernel: every instruction that
+    names an accumulation register sits in an inline-asm block, no compiler
+    instruction uses M0, no scratch, 256 AGPRs reserved and one wave per SIMD."""
+    asm_dd, kernel = asm_acc
+    name = re.search("^(" + kernel + r"\S*):", asm_dd, re.M).group(1)
     start = asm_dd.index(name + ":")
     end = asm_dd.index("; -- End function", start)
     body = asm_dd[start:end]
