@@ -38,27 +38,37 @@ CSCALE = {1: 2, 2: 16, 4: 124}
 PREC_NAME = {1: "complex double", 2: "complex double double", 4: "complex quad double"}
 
 
-# HBM bytes per launch of the benchmark's dominant kernel from two rocprofv3
-# PMC runs (FETCH_SIZE, WRITE_SIZE), scaled by the factors a 2 GiB device copy
-# gives (profiles/eval_d_pinned_kernel_n32_k8_65536pts.md).  Valid only for the
-# kernel sources they were taken with: any change to them reports null.
+# HBM bytes per launch of the evaluation kernels from two rocprofv3 PMC runs
+# (FETCH_SIZE, WRITE_SIZE), scaled by the factors a 2 GiB device copy gives
+# (profiles/eval_*_n32_k8_65536pts.md).  Valid only for the kernel sources
+# (the kernel's file and the headers it compiles) they were taken with: any
+# change to them reports null.
 TRAFFIC = {
     # the double kernel writes H and J once whatever its tiling
     "eval_d_pinned_kernel": {
-        "bytes": 41472341 + 1107454677,   # read + write
-        "sources": {"paper_1505_00383_amd/csrc/eval.hip": "79c12cb91e08a0a4",
-                    "paper_1505_00383_amd/csrc/ph_arith.hpp": "f4b035f2f8fac960",
-                    "paper_1505_00383_amd/csrc/system.cpp": "3d93137455c433f0",
-                    "paper_1505_00383_amd/csrc/ph_internal.hpp": "f7f85e81b4728b64"},
+        "bytes": 41442580 + 1107440640,   # read + write
+        "sources": {"paper_1505_00383_amd/csrc/eval.hip": "a23931464ee6ee46",
+                    "paper_1505_00383_amd/csrc/ph_arith.hpp": "1f4274c3666f77a9",
+                    "paper_1505_00383_amd/csrc/ph_sweep.hpp": "afaab2dda7ee3e60",
+                    "paper_1505_00383_amd/csrc/ph_internal.hpp": "9c1cfcc941ec5fea"},
     },
-    # the general kernel's re-reads depend on its tiling: valid for this one
-    "eval_kernel<2,8,true,true>": {
-        "bytes": 29130984363 + 34249580075,
-        "launch": (1, 8, 4),
-        "sources": {"paper_1505_00383_amd/csrc/eval.hip": "79c12cb91e08a0a4",
-                    "paper_1505_00383_amd/csrc/ph_arith.hpp": "f4b035f2f8fac960",
-                    "paper_1505_00383_amd/csrc/system.cpp": "3d93137455c433f0",
-                    "paper_1505_00383_amd/csrc/ph_internal.hpp": "f7f85e81b4728b64"},
+    # the accumulation-register kernels stage x once per (point tile,
+    # equation group): their reads depend on the tiling
+    "eval_dd_arow_kernel": {
+        "bytes": 81638548 + 2214672256,
+        "launch": (3, 6, 1),
+        "sources": {"paper_1505_00383_amd/csrc/eval_dd.hip": "4f9b4854ab9300ef",
+                    "paper_1505_00383_amd/csrc/ph_arow.hpp": "aee6853f608672f7",
+                    "paper_1505_00383_amd/csrc/ph_arith.hpp": "1f4274c3666f77a9",
+                    "paper_1505_00383_amd/csrc/ph_internal.hpp": "9c1cfcc941ec5fea"},
+    },
+    "eval_qd_arow_kernel": {
+        "bytes": 557253861 + 4429192960,
+        "launch": (3, 6, 4),
+        "sources": {"paper_1505_00383_amd/csrc/eval_qd.hip": "218895931cd72bc2",
+                    "paper_1505_00383_amd/csrc/ph_arow.hpp": "aee6853f608672f7",
+                    "paper_1505_00383_amd/csrc/ph_arith.hpp": "1f4274c3666f77a9",
+                    "paper_1505_00383_amd/csrc/ph_internal.hpp": "9c1cfcc941ec5fea"},
     },
 }
 
@@ -397,17 +407,22 @@ def batch_extra(ph, torch, cpu=True):
     systems = [ph.System(s) for s in sysms]
     base = ph.track_opts(prec=2, mixed=1)
     tuned, tsec = ph.track_autotune(systems, gammas, paths, base, sample=16384)
+    # graph schedule: launches ended by the default time budget, and by a
+    # fixed round count (every wave waits for the slowest at each boundary)
     graph = ph.track_opts(prec=2, mixed=1, schedule=ph.SCHED_GRAPH,
-                          blocks_per_cu=tuned.blocks_per_cu,
-                          rounds_per_launch=tuned.rounds_per_launch)
+                          blocks_per_cu=tuned.blocks_per_cu)
+    graph_fixed = ph.track_opts(prec=2, mixed=1, schedule=ph.SCHED_GRAPH,
+                                blocks_per_cu=tuned.blocks_per_cu, rounds_per_launch=32,
+                                launch_ms=0.0)
     out = {"systems": len(sysms), "cap": int(cap),
            "n_hist": {int(n): int(sum(1 for s in sysms if s.n_var == n))
                       for n in sorted({s.n_var for s in sysms})},
            "tuned": {"schedule": "graph" if tuned.schedule == ph.SCHED_GRAPH else "persistent",
-                     "rounds_per_launch": tuned.rounds_per_launch,
+                     "rounds_per_launch": tuned.rounds_per_launch, "launch_ms": tuned.launch_ms,
                      "blocks_per_cu": tuned.blocks_per_cu, "sample_seconds": tsec}}
     out["tuned_run"], res = time_batch(ph, torch, systems, gammas, paths, tuned, sysms)
     out["graph"], _ = time_batch(ph, torch, systems, gammas, paths, graph, sysms)
+    out["graph_32_rounds_per_launch"], _ = time_batch(ph, torch, systems, gammas, paths, graph_fixed, sysms)
     out["persistent_default"], _ = time_batch(ph, torch, systems, gammas, paths, base, sysms)
     if cpu:
         out["oracle"] = batch_oracle(sysms, gammas, paths, res)
@@ -752,9 +767,16 @@ def main():
                                        inputs=(x2, t2))
             f2 = flops_per_point(sysm, L2)
             log(f"eval prec {L2}: {ms2:.3f} ms")
+            k2 = {1: f"eval_kernel<{L2},8,true,true>", 2: "eval_d_regrow_kernel<8>",
+                  3: {1: "eval_d_pinned_kernel", 2: "eval_dd_arow_kernel",
+                      4: "eval_qd_arow_kernel"}[L2]}.get(cfg2[0] if cfg2 else 3)
+            t2 = traffic_of(k2, cfg2)
             extras[f"eval_prec{L2}"] = {"points_per_s": npts / (ms2 * 1e-3), "ms": ms2,
                                         "fp64_frac": f2 * npts / (ms2 * 1e-3) / PEAK_FP64,
-                                        "launch": cfg2, "finite": ok2}
+                                        "launch": cfg2, "kernel": k2, "traffic": t2,
+                                        "traffic_over_compulsory":
+                                            t2 / (bytes_per_point(sysm, L2) * npts) if t2 else None,
+                                        "finite": ok2}
         extras["eval_n16_d2_hbm_1M_points_double"] = hbm_extra(ph, torch, max(3, args.steps // 4))
         log("hbm-bound eval done")
         extras["eval_pcie_inclusive_host_buffers"] = pcie_extra(ph, torch, S, sysm, L, npts, gamma)
@@ -781,13 +803,18 @@ def summary(result, L):
     error of the mixed endpoints against the oracle's plain track."""
     name = {1: "D", 2: "DD", 4: "QD"}
     ex = result.get("extras", {})
+    rl = result["roofline"]
     out = {"eval_points_per_s": {name[L]: result["value"]},
-           "eval_fp64_frac": {name[L]: result["roofline"]["frac"]}}
+           "eval_fp64_frac": {name[L]: rl["frac"]},
+           "eval_traffic_over_compulsory": {
+               name[L]: rl["traffic"] / (rl["bytes_per_point"] * result["config"]["points"])
+               if rl.get("traffic") else None}}
     for L2 in (1, 2, 4):
         e = ex.get(f"eval_prec{L2}")
         if e:
             out["eval_points_per_s"][name[L2]] = e["points_per_s"]
             out["eval_fp64_frac"][name[L2]] = e["fp64_frac"]
+            out["eval_traffic_over_compulsory"][name[L2]] = e.get("traffic_over_compulsory")
     runs = {}
     if "track_n3_d2_8paths_double" in ex:
         runs["n3_d2_8p_D_plain"] = ex["track_n3_d2_8paths_double"]

@@ -217,6 +217,12 @@ int ph_eval_autotune(ph_system *target, const ph_system *start, const double gam
  *                   and only the count of active waves crosses to the host,
  *                   Section 2, Table 3)
  *   rounds_per_launch   graph schedule: tracker rounds per kernel launch (32)
+ *                   when launch_ms is 0
+ *   launch_ms       graph schedule: every wave of a launch runs rounds until
+ *                   this many milliseconds have passed since it started (at
+ *                   least one round); rounds_per_launch is then ignored.
+ *                   Results do not depend on where launches end (2.0; 0 for
+ *                   a fixed round count)
  *   launches_per_sync   graph schedule: graph replays between reads of the count (8)
  *   blocks_per_cu   workgroups per CU (0: the library's default, 8)
  *   lanes_per_path  lanes that share one path: 4, 8, 16 or 32; 0 selects
@@ -236,6 +242,7 @@ typedef struct {
     int32_t schedule, rounds_per_launch, launches_per_sync, blocks_per_cu;
     int32_t lanes_per_path;
     double tol_res;
+    double launch_ms;
 } ph_track_opts;
 
 /* Counts filled by ph_track when a report pointer is given. */

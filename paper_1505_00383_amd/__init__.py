@@ -44,7 +44,7 @@ class TrackOpts(ctypes.Structure):
                 ("max_steps", ctypes.c_int64), ("schedule", ctypes.c_int32),
                 ("rounds_per_launch", ctypes.c_int32), ("launches_per_sync", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("lanes_per_path", ctypes.c_int32),
-                ("tol_res", ctypes.c_double)]
+                ("tol_res", ctypes.c_double), ("launch_ms", ctypes.c_double)]
 
 
 SCHED_PERSISTENT, SCHED_GRAPH = 0, 1

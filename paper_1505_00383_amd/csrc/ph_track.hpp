@@ -54,6 +54,7 @@ struct TrackArgs {
     double *hist;               // predictor orders 2..4: three older points per lane slot,
     int64_t hist_ld;            //   rows [q][re,im][limb], hist_ld = lane slots of the launch
     int rounds;                 // round schedule: rounds per launch
+    unsigned long long budget;  // round schedule: wall-clock ticks per launch (0: rounds only)
     ph_track_opts o;
     double polish_tol;
     double eps_sing;

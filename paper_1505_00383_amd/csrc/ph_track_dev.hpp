@@ -297,6 +297,7 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
     };
 
     bool retired = false;
+    const long long t_start = a.budget ? wall_clock64() : 0;  // time-budgeted launches
     for (int round = 0; round < max_rounds; ++round) {
         // ---- refill: pop a path from the device queue of this class -------
         if (phase == PH_EMPTY) {
@@ -670,6 +671,11 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
                 finish(bad ? PH_R_NAN : (xe > o.diverge_norm ? PH_R_DIVERGED : PH_R_SUCCESS));
             }
         }
+        // round schedule with a time budget: every wave of the launch stops
+        // after the round in which the budget ran out (wave-uniform clock),
+        // so waves with cheap rounds do not wait for the others at the end
+        // of a launch of a fixed round count
+        if (a.budget && (unsigned long long)(wall_clock64() - t_start) >= a.budget) break;
     }
     S.phase = phase;
     S.sidx = sidx;

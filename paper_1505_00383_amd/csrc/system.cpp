@@ -551,5 +551,6 @@ extern "C" int ph_track_opts_default(ph_track_opts *o)
     o->blocks_per_cu = 0;
     o->lanes_per_path = 0;
     o->tol_res = 1e-6;
+    o->launch_ms = 2.0;
     return PH_OK;
 }

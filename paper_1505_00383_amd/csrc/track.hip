@@ -77,7 +77,8 @@ static int check_opts(const ph_track_opts &o)
     if (o.max_newton < 1 || o.expand_after < 1 || o.polish_max < 0 || o.max_steps < 0)
         return fail(PH_EINVAL, "invalid iteration counts in opts");
     if (!(o.h_init > 0) || !(o.h_max > 0) || !(o.h_min >= 0) || !(o.shrink > 0 && o.shrink < 1) ||
-        !(o.expand >= 1) || !(o.tol_dx > 0) || !(o.diverge_norm > 0) || !(o.tol_res >= 0))
+        !(o.expand >= 1) || !(o.tol_dx > 0) || !(o.diverge_norm > 0) || !(o.tol_res >= 0) ||
+        !(o.launch_ms >= 0) || !(o.launch_ms <= 60000))
         return fail(PH_EINVAL, "invalid step-control constants in opts");
     if (o.lanes_per_path != 0 && o.lanes_per_path != 4 && o.lanes_per_path != 8 &&
         o.lanes_per_path != 16 && o.lanes_per_path != 32)
@@ -369,6 +370,13 @@ static int track_impl(int nsys, const ph_system *const *targets, const ph_system
         if (rc) return rc;
         a.state = bstate.p;
         a.rounds = std::max(1, opts->rounds_per_launch);
+        if (opts->launch_ms > 0) {
+            int khz = 0;  // wall clock of wall_clock64()
+            PH_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+            if (khz <= 0) khz = 100000;
+            a.budget = (unsigned long long)std::max(1.0, opts->launch_ms * khz);
+            a.rounds = 0x7fffffff;
+        }
         // capture and replay on a private stream (the legacy default stream
         // cannot be captured), ordered after the caller's stream
         StreamGuard cs;
@@ -531,17 +539,20 @@ extern "C" int ph_track_autotune(int32_t nsys, const ph_system *const *targets, 
             char line[512], tag[16];
             unsigned long long k = 0;
             int sch = 0, rnd = 0, bpc = 0, lanes = 0;
-            double sec = 0;
+            double lms = 0, sec = 0;
             bool found = false;
             ph_track_opts o = *opts;
-            // one entry per line; lines of other tags (the evaluation's) are skipped
+            // one entry per line "track <key> <schedule> <rounds> <blocks per CU>
+            // <lanes> <launch ms> <seconds>"; lines of other tags are skipped
             while (std::fgets(line, sizeof line, f)) {
-                if (std::sscanf(line, "%15s %llx %d %d %d %d %lf", tag, &k, &sch, &rnd, &bpc, &lanes, &sec) == 7 &&
+                if (std::sscanf(line, "%15s %llx %d %d %d %d %lf %lf", tag, &k, &sch, &rnd, &bpc, &lanes, &lms,
+                                &sec) == 8 &&
                     std::strcmp(tag, "track") == 0 && k == key) {
                     o.schedule = sch;
                     o.rounds_per_launch = rnd;
                     o.blocks_per_cu = bpc;
                     o.lanes_per_path = lanes;
+                    o.launch_ms = lms;
                     found = true;
                 }
             }
@@ -574,15 +585,18 @@ extern "C" int ph_track_autotune(int32_t nsys, const ph_system *const *targets, 
     // equation's term sweeps: more waves and shorter rounds for few paths)
     int np_max = 4;
     while (np_max < maxn) np_max *= 2;
-    struct Cand { int sch, rnd, bpc, lanes; };
+    // (graph schedule: fixed round counts and time budgets per launch)
+    struct Cand { int sch, rnd, bpc, lanes; double lms; };
     std::vector<Cand> cands;
     for (int lanes : {0, 2 * np_max, 4 * np_max}) {
         if (lanes > 32) continue;
         const int lcap = (int)std::max<size_t>(
             1, (160 * 1024) / track_lds_bytes(opts->prec, opts->mixed, lanes ? lanes : np_max));
         for (int bpc : {2, 4, 8, 12, 16})
-            if (bpc <= lcap || bpc == 2) cands.push_back({PH_SCHED_PERSISTENT, opts->rounds_per_launch, bpc, lanes});
-        for (int rnd : {8, 32, 128}) cands.push_back({PH_SCHED_GRAPH, rnd, std::min(8, lcap), lanes});
+            if (bpc <= lcap || bpc == 2)
+                cands.push_back({PH_SCHED_PERSISTENT, opts->rounds_per_launch, bpc, lanes, opts->launch_ms});
+        for (int rnd : {8, 32, 128}) cands.push_back({PH_SCHED_GRAPH, rnd, std::min(8, lcap), lanes, 0.0});
+        for (double lms : {1.0, 2.0, 4.0}) cands.push_back({PH_SCHED_GRAPH, 32, std::min(8, lcap), lanes, lms});
     }
     double best = 1e300;
     ph_track_opts bo = *opts;
@@ -592,6 +606,7 @@ extern "C" int ph_track_autotune(int32_t nsys, const ph_system *const *targets, 
         o.rounds_per_launch = c.rnd;
         o.blocks_per_cu = c.bpc;
         o.lanes_per_path = c.lanes;
+        o.launch_ms = c.lms;
         ph_track_report r;
         rc = track_impl(nsys, targets, nullptr, gammas, off.data(), ids.data(), nullptr, ns, &o,
                         (double *)bx.p, (int8_t *)bst.p, nullptr, nullptr, &r, st);
@@ -605,8 +620,8 @@ extern "C" int ph_track_autotune(int32_t nsys, const ph_system *const *targets, 
     if (best_seconds) *best_seconds = best;
     if (cache) {
         if (FILE *f = std::fopen(cache, "a")) {
-            std::fprintf(f, "track %llx %d %d %d %d %.6f\n", (unsigned long long)key, bo.schedule,
-                         bo.rounds_per_launch, bo.blocks_per_cu, bo.lanes_per_path, best);
+            std::fprintf(f, "track %llx %d %d %d %d %.3f %.6f\n", (unsigned long long)key, bo.schedule,
+                         bo.rounds_per_launch, bo.blocks_per_cu, bo.lanes_per_path, bo.launch_ms, best);
             std::fclose(f);
         }
     }

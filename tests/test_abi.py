@@ -44,14 +44,14 @@ def test_opts_default_host_only(lib):
                    [("max_steps", ctypes.c_int64)] + \
                    [(n, ctypes.c_int32) for n in ("schedule", "rounds_per_launch", "launches_per_sync",
                                                    "blocks_per_cu", "lanes_per_path")] + \
-                   [("tol_res", ctypes.c_double)]
+                   [("tol_res", ctypes.c_double), ("launch_ms", ctypes.c_double)]
     o = Opts()
     assert lib.ph_track_opts_default(ctypes.byref(o)) == 0
     assert (o.prec, o.max_newton, o.expand_after, o.polish_max) == (1, 3, 3, 8)
     assert (o.h_init, o.h_min, o.h_max, o.shrink, o.expand) == (0.01, 1e-10, 0.1, 0.5, 1.5)
     assert (o.tol_dx, o.diverge_norm, o.max_steps) == (1e-8, 1e8, 100000)
     assert (o.schedule, o.rounds_per_launch, o.launches_per_sync, o.blocks_per_cu) == (0, 32, 8, 0)
-    assert o.lanes_per_path == 0 and o.tol_res == 1e-6
+    assert o.lanes_per_path == 0 and o.tol_res == 1e-6 and o.launch_ms == 2.0
     assert ctypes.sizeof(Opts) == ctypes.sizeof(ph.TrackOpts)
     assert lib.ph_track_opts_default(None) == -1
 

@@ -210,13 +210,17 @@ def test_graph_schedule_matches_persistent_bitwise():
     S = ph.System(s)
     a = ph.track(S, g, 500, ph.track_opts(prec=2, mixed=1))
     b = ph.track(S, g, 500, ph.track_opts(prec=2, mixed=1, schedule=ph.SCHED_GRAPH,
-                                          rounds_per_launch=5, launches_per_sync=3))
+                                          rounds_per_launch=5, launches_per_sync=3, launch_ms=0.0))
+    # launches ended by a time budget (here 0.05 ms: a few rounds each)
+    c = ph.track(S, g, 500, ph.track_opts(prec=2, mixed=1, schedule=ph.SCHED_GRAPH,
+                                          launches_per_sync=3, launch_ms=0.05))
     print(f"[gpu] graph schedule: persistent {a['report']['seconds']:.3f}s graph "
-          f"{b['report']['seconds']:.3f}s", flush=True)
-    assert np.array_equal(a["x_end"].cpu().numpy(), b["x_end"].cpu().numpy())
-    for k in ("status", "reason", "steps"):
-        assert np.array_equal(a[k], b[k])
-    assert a["report"]["newton_its"] == b["report"]["newton_its"]
+          f"{b['report']['seconds']:.3f}s timed launches {c['report']['seconds']:.3f}s", flush=True)
+    for r in (b, c):
+        assert np.array_equal(a["x_end"].cpu().numpy(), r["x_end"].cpu().numpy())
+        for k in ("status", "reason", "steps"):
+            assert np.array_equal(a[k], r[k])
+        assert a["report"]["newton_its"] == r["report"]["newton_its"]
 
 
 @pytest.mark.parametrize("schedule", [0, 1])
@@ -230,7 +234,8 @@ def test_batch_lane_classes(schedule):
         gammas.append(synth.unit_complex(rng))
         paths.append(np.sort(rng.choice(2 ** n, size=min(npath, 2 ** n), replace=False)))
     res = ph.track_batch([ph.System(x) for x in systems], gammas, paths,
-                         ph.track_opts(prec=2, mixed=1, schedule=schedule, rounds_per_launch=16))
+                         ph.track_opts(prec=2, mixed=1, schedule=schedule, rounds_per_launch=16,
+                                       launch_ms=0.0))
     for k, sy in enumerate(systems):
         _parity(sy, gammas[k], 2, _member(res, k, sy.n_var, 2), paths[k],
                 note=f"class batch n={sy.n_var} schedule={schedule}")
@@ -342,7 +347,7 @@ def test_order4_graph_schedule_matches_persistent_bitwise():
     S = ph.System(s)
     a = ph.track(S, g, 300, ph.track_opts(prec=2, mixed=1, predictor_order=4))
     b = ph.track(S, g, 300, ph.track_opts(prec=2, mixed=1, predictor_order=4, schedule=ph.SCHED_GRAPH,
-                                          rounds_per_launch=3, launches_per_sync=5))
+                                          rounds_per_launch=3, launches_per_sync=5, launch_ms=0.0))
     import torch
     assert (a["status"] == b["status"]).all() and (a["steps"] == b["steps"]).all()
     assert torch.equal(a["x_end"], b["x_end"])
