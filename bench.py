@@ -56,7 +56,7 @@ TRAFFIC = {
     # equation group): their reads depend on the tiling
     "eval_dd_arow_kernel": {
         "bytes": 81638548 + 2214672256,
-        "launch": (3, 6, 1),
+        "launch": (3, 4, 1),
         "sources": {"paper_1505_00383_amd/csrc/eval_dd.hip": "4f9b4854ab9300ef",
                     "paper_1505_00383_amd/csrc/ph_arow.hpp": "aee6853f608672f7",
                     "paper_1505_00383_amd/csrc/ph_arith.hpp": "1f4274c3666f77a9",
@@ -64,7 +64,7 @@ TRAFFIC = {
     },
     "eval_qd_arow_kernel": {
         "bytes": 557253861 + 4429192960,
-        "launch": (3, 6, 4),
+        "launch": (3, 4, 4),
         "sources": {"paper_1505_00383_amd/csrc/eval_qd.hip": "218895931cd72bc2",
                     "paper_1505_00383_amd/csrc/ph_arow.hpp": "aee6853f608672f7",
                     "paper_1505_00383_amd/csrc/ph_arith.hpp": "1f4274c3666f77a9",
@@ -78,6 +78,10 @@ def traffic_of(kernel, launch=None):
     t = TRAFFIC.get(kernel)
     if t is None:
         return None
+    if launch is not None and kernel in ("eval_dd_arow_kernel", "eval_qd_arow_kernel"):
+        # these kernels run at most four waves per workgroup (one per SIMD):
+        # a larger configured count launches four
+        launch = (launch[0], min(launch[1], 4), launch[2])
     if "launch" in t and (launch is None or tuple(launch) != t["launch"]):
         return None
     for path, sha in t["sources"].items():

@@ -539,16 +539,41 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
                 {
                     R<LS> inv = r_div<LS>(r_from<LS>(1.0), rkk);
                     C<LS> q = c_mul_r<LS>(wk, inv);
+                    // projection of column j on q: r = q^H w_j (group sum),
+                    // w_j -= r q; column k is dead after step k, so R(k, j)
+                    // goes to row j of it
+                    auto proj = [&](int j) -> C<LS> {
+                        double *ej = W(j, i);
+                        C<LS> wj = lds_get<LS>(ej);
+                        C<LS> r = gsum_c<NP, LS>(c_cmul<LS>(q, wj));
+                        lds_put<LS>(ej, c_sub<LS>(wj, c_mul<LS>(r, q)));
+                        return r;
+                    };
+                    if constexpr (LS == 1) {
+                        // FP64 solves are latency bound: four columns at a
+                        // time, so their group sums interleave; the stores
+                        // of R(k, j) follow, one per lane
+                        int j = k + 1;
 #pragma unroll 1
-                    for (int j = k + 1; j <= NP; ++j) {
-                        if (j == n && j < NP) j = NP;  // skip the padding columns
-                        {
-                            double *ej = W(j, i);
-                            C<LS> wj = lds_get<LS>(ej);
-                            C<LS> r = gsum_c<NP, LS>(c_cmul<LS>(q, wj));
-                            lds_put<LS>(ej, c_sub<LS>(wj, c_mul<LS>(r, q)));
+                        for (; j + 3 < n; j += 4) {
+                            const C<LS> r0 = proj(j), r1 = proj(j + 1), r2 = proj(j + 2), r3 = proj(j + 3);
+                            const int d = i - j;
+                            if (d >= 0 && d < 4)
+                                lds_put<LS>(W(k, i), d == 0 ? r0 : (d == 1 ? r1 : (d == 2 ? r2 : r3)));
+                        }
+#pragma unroll 1
+                        for (; j < n; ++j) {
+                            const C<LS> r = proj(j);
+                            if (i == j) lds_put<LS>(W(k, j), r);
+                        }
+                        const C<LS> r = proj(NP);
+                        if (i == k) acc = r;
+                    } else {
+#pragma unroll 1
+                        for (int j = k + 1; j <= NP; ++j) {
+                            if (j == n && j < NP) j = NP;  // skip the padding columns
+                            const C<LS> r = proj(j);
                             if (i == k && j == NP) acc = r;
-                            // column k is dead after step k: R(k, j) goes to row j of it
                             if (j < NP && i == j) lds_put<LS>(W(k, j), r);
                         }
                     }

@@ -64,6 +64,13 @@ def test_traffic_guard(monkeypatch):
     assert bench.traffic_of("k_tiled") is None
     assert bench.traffic_of("k_stale") is None
     assert bench.traffic_of("unknown") is None
+    # the accumulation-register kernels launch at most four waves per
+    # workgroup: a larger configured count is the same launch
+    monkeypatch.setattr(bench, "TRAFFIC", {"eval_dd_arow_kernel": {"bytes": 7, "launch": (3, 4, 1),
+                                                                   "sources": {path: sha}}})
+    assert bench.traffic_of("eval_dd_arow_kernel", (3, 8, 1)) == 7
+    assert bench.traffic_of("eval_dd_arow_kernel", (3, 6, 1)) == 7
+    assert bench.traffic_of("eval_dd_arow_kernel", (3, 2, 1)) is None
 
 
 def test_mgs_flops_counts_by_hand():

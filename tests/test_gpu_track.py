@@ -241,6 +241,33 @@ def test_batch_lane_classes(schedule):
                 note=f"class batch n={sy.n_var} schedule={schedule}")
 
 
+def test_batch_shared_sweeps_bitwise():
+    """A batch of systems with n = 3, 6, 12 and 5 (4, 8, 16 and 8 natural
+    lanes) under 32 lanes per path, where eight, four, two and four lanes
+    share each equation's term sweeps, against 16 lanes per path (four, two,
+    one and two): endpoints, status and step counts bitwise equal, under both
+    schedules.  (This batch is small enough that the default doubles the
+    natural counts, so the natural counts alone are not selectable here; the
+    single-system test compares them.)"""
+    import torch
+    rng = np.random.default_rng(19)
+    systems, gammas, paths = [], [], []
+    for n, nt, npath in ((3, 5, 8), (6, 7, 40), (12, 6, 24), (5, 5, 32)):
+        eqs = [synth._equation_with_anchor(rng, list(range(n)), i, 2, nt) for i in range(n)]
+        systems.append(synth.system_from_terms(n, eqs))
+        gammas.append(synth.unit_complex(rng))
+        paths.append(np.sort(rng.choice(2 ** n, size=min(npath, 2 ** n), replace=False)))
+    handles = [ph.System(x) for x in systems]
+    for L, mixed in ((2, 1), (4, 0)):
+        base = ph.track_batch(handles, gammas, paths, ph.track_opts(prec=L, mixed=mixed, lanes_per_path=16))
+        for sched in (ph.SCHED_PERSISTENT, ph.SCHED_GRAPH):
+            r = ph.track_batch(handles, gammas, paths,
+                               ph.track_opts(prec=L, mixed=mixed, lanes_per_path=32, schedule=sched))
+            assert (base["status"] == r["status"]).all() and (base["steps"] == r["steps"]).all()
+            assert torch.equal(base["x_end"], r["x_end"]), (L, mixed, sched)
+        assert (base["status"] == 1).mean() > 0.9
+
+
 def _distinct(X, ok):
     Z = X[ok][..., 0, 0] + 1j * X[ok][..., 1, 0]
     key = np.round(Z / 1e-6)
