@@ -584,16 +584,18 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        // back substitution R dx = r_rhs, column oriented: lane i keeps acc_i
+        // back substitution R dx = r_rhs, column oriented: lane i keeps acc_i;
+        // every lane forms 1 / R(i, i) first, side by side, so that no
+        // division sits on the serial chain of the substitution
         C<LS> dxi = c_zero<LS>();
+        R<LS> inv_i = r_zero<LS>();
+        if (!sing && i < n) inv_i = r_div<LS>(r_from<LS>(1.0), lds_get<LS>(W(i, i)).re);
 #pragma unroll 1
         for (int k = n - 1; k >= 0; --k) {
             if (!sing) {
                 C<LS> dk = c_zero<LS>();
                 if (i == k) {
-                    R<LS> rkk = lds_get<LS>(W(k, k)).re;
-                    R<LS> inv = r_div<LS>(r_from<LS>(1.0), rkk);
-                    dk = c_mul_r<LS>(acc, inv);
+                    dk = c_mul_r<LS>(acc, inv_i);
                     dxi = dk;
                 }
                 dk = shfl_c<LS>(dk, base + k);
