@@ -144,8 +144,13 @@ int ph_eval_prepare(ph_system *target, const ph_system *start, int32_t prec,
  * ph_eval_set_config -- pin the kernel and tiling ph_eval_jac uses for
  * (target, start, prec): kernel 0 automatic, 1 general (Jacobian row
  * accumulated in the output), 2 register-resident row (double, n_var <= 32),
- * 3 double fast path (n_var <= 32, <= 8 factors per term, exponents <= 4)
- * with the row in pinned registers, 4 the same with a compiler-held row,
+ * 3 fast path (n_var <= 32, <= 8 factors per term, exponents <= 4 and, in
+ * double double and quad double, x and its powers fitting the 160 KB of LDS)
+ * with the Jacobian row on chip: in pinned registers (double), in the
+ * accumulation registers (double double: one point per lane; quad double:
+ * one point per two lanes), at most four waves per workgroup in double double
+ * and quad double (a larger count launches four), 4 the double fast path
+ * with a compiler-held row,
  * 5 the paper's unfused design (coeff, mon and sum kernels with the
  * coefficients and the k + 1 products of every term and point stored in
  * device memory between them; an ablation of the fused kernels, whose
@@ -339,9 +344,10 @@ int ph_track_batch(int32_t nsys, const ph_system *const *targets, const double *
  * ph_track_autotune -- choose the launch shape of ph_track_batch (and of
  * ph_track with a total-degree start) for this batch: tracks a sample of
  * about `sample` paths (each system's first ones, in proportion to its path
- * count) under each candidate (schedule, rounds_per_launch, blocks_per_cu,
- * lanes_per_path)
- * and writes *opts with the fastest into *tuned (every other field copied).
+ * count) under each candidate (schedule; for the graph schedule a fixed
+ * rounds_per_launch of 8, 32 or 128 or a launch_ms of 1, 2 or 4; blocks_per_cu;
+ * lanes_per_path: the natural count, twice or four times it) and writes *opts
+ * with the fastest into *tuned (every other field copied).
  * With PH_AUTOTUNE_CACHE naming a file, a previous choice for the same
  * systems, path counts, prec and mixed is read from it instead of timing, and
  * a new choice is appended.  best_seconds (nullable) receives the sample's
