@@ -313,6 +313,23 @@ __device__ __forceinline__ C<1> ldsc(const char *__restrict__ xb, uint32_t off, 
     return c_from<1>(p[lane], p[64 + lane]);
 }
 
+// row[j] += q * d (complex) as four FMAs into the row entry
+__device__ __forceinline__ void regrow_cfma(RegRow &r, int j, const C<1> &q, const C<1> &d)
+{
+    const unsigned long long a = ((unsigned long long)r.rh[j] << 32) | r.rl[j];
+    const unsigned long long b = ((unsigned long long)r.ih[j] << 32) | r.il[j];
+    double x = __builtin_fma(q.re.v[0], d.re.v[0], __builtin_bit_cast(double, a));
+    double y = __builtin_fma(q.re.v[0], d.im.v[0], __builtin_bit_cast(double, b));
+    x = __builtin_fma(-q.im.v[0], d.im.v[0], x);
+    y = __builtin_fma(q.im.v[0], d.re.v[0], y);
+    const unsigned long long xa = __builtin_bit_cast(unsigned long long, x);
+    const unsigned long long yb = __builtin_bit_cast(unsigned long long, y);
+    r.rl[j] = (unsigned)xa;
+    r.rh[j] = (unsigned)(xa >> 32);
+    r.il[j] = (unsigned)yb;
+    r.ih[j] = (unsigned)(yb >> 32);
+}
+
 __device__ __forceinline__ void regrow_fma(RegRow &r, int j, double e, const C<1> &d)
 {
     const unsigned long long a = ((unsigned long long)r.rh[j] << 32) | r.rl[j];
@@ -338,6 +355,7 @@ struct VecRow {
         r.ih = 0;
     }
     __device__ __forceinline__ void fma(int j2, double e, const C<1> &d) { regrow_fma(r, j2 >> 1, e, d); }
+    __device__ __forceinline__ void cfma(int j2, const C<1> &q, const C<1> &d) { regrow_cfma(r, j2 >> 1, q, d); }
     __device__ __forceinline__ void get(int j, double &re, double &im)
     {
         re = __builtin_bit_cast(double, ((unsigned long long)r.rh[j] << 32) | r.rl[j]);
@@ -372,6 +390,20 @@ struct PinRow {
                      "s_set_gpr_idx_off"
                      :
                      : "s"(j2), "s"(e), "v"(d.re.v[0]), "v"(d.im.v[0])
+                     : PH_PIN_CLOBBERS);
+    }
+    // row[j] += q * d (complex): four FMAs into the row, the product never
+    // rounded on its own (a factor with exponent 1 needs no scaling)
+    __device__ __forceinline__ void cfma(int j2, const C<1> &q, const C<1> &d)
+    {
+        asm volatile("s_set_gpr_idx_on %0, gpr_idx(SRC2,DST)\n\t"
+                     "v_fma_f64 v[128:129], %1, %3, v[128:129]\n\t"
+                     "v_fma_f64 v[192:193], %1, %4, v[192:193]\n\t"
+                     "v_fma_f64 v[128:129], -%2, %4, v[128:129]\n\t"
+                     "v_fma_f64 v[192:193], %2, %3, v[192:193]\n\t"
+                     "s_set_gpr_idx_off"
+                     :
+                     : "s"(j2), "v"(q.re.v[0]), "v"(q.im.v[0]), "v"(d.re.v[0]), "v"(d.im.v[0])
                      : PH_PIN_CLOBBERS);
     }
     __device__ __forceinline__ void get(int j, double &re, double &im)
@@ -409,6 +441,18 @@ struct PinRow16 {
                      "s_set_gpr_idx_off"
                      :
                      : "s"(j2), "s"(e), "v"(d.re.v[0]), "v"(d.im.v[0])
+                     : PH_PIN16_CLOBBERS);
+    }
+    __device__ __forceinline__ void cfma(int j2, const C<1> &q, const C<1> &d)
+    {
+        asm volatile("s_set_gpr_idx_on %0, gpr_idx(SRC2,DST)\n\t"
+                     "v_fma_f64 v[64:65], %1, %3, v[64:65]\n\t"
+                     "v_fma_f64 v[96:97], %1, %4, v[96:97]\n\t"
+                     "v_fma_f64 v[64:65], -%2, %4, v[64:65]\n\t"
+                     "v_fma_f64 v[96:97], %2, %3, v[96:97]\n\t"
+                     "s_set_gpr_idx_off"
+                     :
+                     : "s"(j2), "v"(q.re.v[0]), "v"(q.im.v[0]), "v"(d.re.v[0]), "v"(d.im.v[0])
                      : PH_PIN16_CLOBBERS);
     }
     __device__ __forceinline__ void get(int j, double &re, double &im)
@@ -465,9 +509,10 @@ __device__ __forceinline__ DHead dfast_head(const DTerm *__restrict__ r)
 // balanced tree; then one forward pass carries the running prefix product
 // and issues, at each factor, the cross product with the suffix beside the
 // next prefix product, so that only one prefix product is ever live.
-// 3K - 3 + M complex products, the cost model's count.  A term's factors
-// are distinct unknowns, so the order of its row updates does not change
-// any result.
+// 3K - 3 + M complex products, the cost model's count (the cross products
+// of the K - M factors with exponent 1 are fused into their row updates).
+// A term's factors are distinct unknowns, so the order of its row updates
+// does not change any result.
 template <int K, int M, class Row>
 __device__ __forceinline__ void dfast_sweep(const DHead &h, const DTerm *__restrict__ rnext, DHead &hnext,
                                             const char *__restrict__ xb, int lane, C<1> cf,
@@ -493,13 +538,20 @@ __device__ __forceinline__ void dfast_sweep(const DHead &h, const DTerm *__restr
         }
         cf = c_mul<1>(cf, pw[0]);
     }
-    // q = c x_0 ... x_{l-1} (times the powers); partial l = q * sf[l+1]
+    // q = c x_0 ... x_{l-1} (times the powers); partial l = q * sf[l+1],
+    // scaled by the exponent a_l >= 2 for the first M factors; a factor with
+    // exponent 1 has q * sf[l+1] accumulated straight into the row (four FMAs
+    // in place of a product and two FMAs)
     C<1> q = cf;
 #pragma unroll
     for (int l = 0; l < K - 1; ++l) {
-        const C<1> part = c_mul<1>(q, sf[l + 1]);
+        if (l >= M) {
+            row.cfma((int)h.j2[l], q, sf[l + 1]);
+        } else {
+            const C<1> part = c_mul<1>(q, sf[l + 1]);
+            row.fma((int)h.j2[l], h.a[l], part);
+        }
         q = c_mul<1>(q, xv[l]);
-        row.fma((int)h.j2[l], h.a[l], part);
     }
     v = c_add<1>(v, c_mul<1>(q, xv[K - 1]));
     row.fma((int)h.j2[K - 1], h.a[K - 1], q);
