@@ -229,7 +229,10 @@ int ph_eval_autotune(ph_system *target, const ph_system *start, const double gam
  *                   Results do not depend on where launches end (2.0; 0 for
  *                   a fixed round count)
  *   launches_per_sync   graph schedule: graph replays between reads of the count (8)
- *   blocks_per_cu   workgroups per CU (0: the library's default, 8)
+ *   blocks_per_cu   workgroups per CU (0: the library's default, 8); never
+ *                   more than the launch's kernel fits on a CU at once
+ *                   (registers, LDS), so every workgroup of a launch starts
+ *                   with it
  *   lanes_per_path  lanes that share one path: 4, 8, 16 or 32; 0 selects
  *                   the natural count (the next power of two >= n, at least
  *                   4), doubled when the paths at their natural count would
@@ -298,7 +301,7 @@ int ph_track(const ph_system *target, const ph_system *start, const double gamma
  * ph_track, with these differences:
  *   - the device scratch of a call (counters and work queue, the system
  *     descriptor, the predictor history of predictor_order >= 2) lives in one
- *     library-owned device buffer of 32 MiB per GPU, created when the library
+ *     library-owned device buffer of 16 MiB per GPU, created when the library
  *     is loaded on that GPU and held until the process ends; the call makes no
  *     device allocation and frees nothing;
  *   - opts->schedule must be PH_SCHED_PERSISTENT (PH_EUNSUPPORTED otherwise);
@@ -306,7 +309,8 @@ int ph_track(const ph_system *target, const ph_system *start, const double gamma
  *     ph_eval_prepare (PH_EINVAL otherwise; it builds its term table);
  *   - PH_EINVAL when the predictor history of the launch (3 * 2 * prec * 8
  *     bytes per lane slot, 64 slots per workgroup, predictor_order >= 2 only)
- *     exceeds the buffer's 32 MiB - 64 KiB: lower opts->blocks_per_cu.
+ *     exceeds the buffer's 16 MiB - 64 KiB (quad double at more than about
+ *     five workgroups per CU): lower opts->blocks_per_cu.
  * Every call on a GPU uses that GPU's one buffer, which keeps the previous
  * call's contents (the call clears its counters itself): calls that overlap
  * on one GPU (other threads, other streams) race and must be serialised by

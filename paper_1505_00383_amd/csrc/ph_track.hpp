@@ -60,11 +60,14 @@ struct TrackArgs {
     double eps_sing;
 };
 
-int track_launch(const TrackArgs &a, int prec, int kmax, int blocks, size_t lds, hipStream_t st);
+// occ == nullptr: launch the tracker kernel; else store the number of its
+// workgroups that fit one CU at once (registers, LDS) and launch nothing.
+int track_launch(const TrackArgs &a, int prec, int kmax, int blocks, size_t lds, hipStream_t st,
+                 int *occ = nullptr);
 // Per (residual limbs L, FP64 solves) launchers and slot-state helpers,
 // instantiated in track_unit.hip.
 template <int L, bool MIXED>
-int track_launch_t(const TrackArgs &a, int kmax, int blocks, size_t lds, hipStream_t st);
+int track_launch_t(const TrackArgs &a, int kmax, int blocks, size_t lds, hipStream_t st, int *occ);
 template <int L>
 size_t slot_bytes_t();
 template <int L>

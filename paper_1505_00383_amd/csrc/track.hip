@@ -11,19 +11,19 @@ namespace ph {
 
 __global__ void clear_counter_kernel(unsigned int *c) { *c = 0u; }
 
-int track_launch(const TrackArgs &a, int prec, int kmax, int blocks, size_t lds, hipStream_t st)
+int track_launch(const TrackArgs &a, int prec, int kmax, int blocks, size_t lds, hipStream_t st, int *occ)
 {
     if (a.o.mixed) {
         switch (prec) {
-        case 1: return track_launch_t<1, true>(a, kmax, blocks, lds, st);
-        case 2: return track_launch_t<2, true>(a, kmax, blocks, lds, st);
-        default: return track_launch_t<4, true>(a, kmax, blocks, lds, st);
+        case 1: return track_launch_t<1, true>(a, kmax, blocks, lds, st, occ);
+        case 2: return track_launch_t<2, true>(a, kmax, blocks, lds, st, occ);
+        default: return track_launch_t<4, true>(a, kmax, blocks, lds, st, occ);
         }
     }
     switch (prec) {
-    case 1: return track_launch_t<1, false>(a, kmax, blocks, lds, st);
-    case 2: return track_launch_t<2, false>(a, kmax, blocks, lds, st);
-    default: return track_launch_t<4, false>(a, kmax, blocks, lds, st);
+    case 1: return track_launch_t<1, false>(a, kmax, blocks, lds, st, occ);
+    case 2: return track_launch_t<2, false>(a, kmax, blocks, lds, st, occ);
+    default: return track_launch_t<4, false>(a, kmax, blocks, lds, st, occ);
     }
 }
 
@@ -121,7 +121,7 @@ struct DevBuf {
 // GPU, held until the process ends.  Host code never passes the array's name
 // to a kernel or a copy (on the host it is only a stand-in symbol); it uses
 // the device address that hipGetSymbolAddress returns for the current device.
-constexpr size_t NOALLOC_BYTES = size_t(32) << 20;
+constexpr size_t NOALLOC_BYTES = size_t(16) << 20;
 constexpr size_t NOALLOC_DESC_OFF = 4096;          // after the counters
 constexpr size_t NOALLOC_HIST_OFF = size_t(64) << 10;
 static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
@@ -320,26 +320,50 @@ static int track_impl(int nsys, const ph_system *const *targets, const ph_system
     a.polish_tol = opts->polish_tol < 0 ? 8.0 * unit_roundoff(prec) : opts->polish_tol;
     a.eps_sing = eps_singular(opts->mixed ? 1 : prec);
 
-    // ---- blocks: per class proportional to its work, capped by residency
+    // ---- blocks: per class proportional to its work, capped by residency:
+    // no more workgroups than fit the CUs at once, so that every workgroup of
+    // a launch starts with it (a round launch whose last workgroups waited
+    // for the first ones to end would run twice its budget, mostly idle)
+    const size_t lds = track_lds_bytes(prec, opts->mixed, np_max);
     int per_cu = opts->blocks_per_cu > 0 ? opts->blocks_per_cu : 8;
+    {
+        int occ = 0;
+        rc = track_launch(a, prec, kmax, 0, lds, st, &occ);
+        if (rc) return rc;
+        if (occ > 0) per_cu = std::min(per_cu, occ);
+    }
     int cap = cus * per_cu;
     if (const char *env = std::getenv("PH_TRACK_BLOCKS")) {
         const int e = std::atoi(env);
         if (e > 0) cap = std::min(cap, e);
     }
+    // the shares are rounded down and then trimmed so that the classes
+    // together never exceed the cap (one workgroup over it would start only
+    // when a whole CU's worth had ended)
     double wsum = work[0] + work[1] + work[2] + work[3];
+    int nbc[4] = {0, 0, 0, 0};
     int blocks = 0;
     for (int c = 0; c < 4; ++c) {
-        a.cls[c].queue = ctr + 10 + c;
-        int nb = 0;
         if (a.cls[c].total > 0) {
             const int64_t need = (a.cls[c].total + (64 / class_np[c]) - 1) / (64 / class_np[c]);
-            nb = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)std::ceil(cap * work[c] / wsum)));
+            nbc[c] = (int)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)std::floor(cap * work[c] / wsum)));
         }
-        blocks += nb;
+        blocks += nbc[c];
+    }
+    while (blocks > cap) {
+        int big = 0;
+        for (int c = 1; c < 4; ++c)
+            if (nbc[c] > nbc[big]) big = c;
+        if (nbc[big] <= 1) break;
+        --nbc[big];
+        --blocks;
+    }
+    blocks = 0;
+    for (int c = 0; c < 4; ++c) {
+        a.cls[c].queue = ctr + 10 + c;
+        blocks += nbc[c];
         a.cls[c].block_end = blocks;
     }
-    const size_t lds = track_lds_bytes(prec, opts->mixed, np_max);
     if (opts->predictor_order > 1) {
         // three older points per lane slot, kept across launches
         a.hist_ld = (int64_t)blocks * 64;

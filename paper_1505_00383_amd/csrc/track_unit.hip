@@ -7,9 +7,16 @@
 
 namespace ph {
 
+// occ == nullptr: launch; else store in *occ how many workgroups of the
+// kernel that would be launched fit one CU at once, and launch nothing
 template <int L, bool MIXED, int KMAX, int NPSEL>
-static int launch_k(const TrackArgs &a, int blocks, size_t lds, hipStream_t st)
+static int launch_k(const TrackArgs &a, int blocks, size_t lds, hipStream_t st, int *occ)
 {
+    if (occ) {
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(occ, track_kernel<L, KMAX, MIXED, NPSEL>, 64, lds);
+        if (e != hipSuccess) return hip_fail(e, "track kernel occupancy");
+        return PH_OK;
+    }
     hipLaunchKernelGGL((track_kernel<L, KMAX, MIXED, NPSEL>), dim3(blocks), dim3(64), lds, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "track kernel launch");
@@ -18,23 +25,23 @@ static int launch_k(const TrackArgs &a, int blocks, size_t lds, hipStream_t st)
 
 // several lane-count classes up to NPMAX in one launch
 template <int L, bool MIXED, int NPMAX>
-static int launch_n(const TrackArgs &a, int kmax, int blocks, size_t lds, hipStream_t st)
+static int launch_n(const TrackArgs &a, int kmax, int blocks, size_t lds, hipStream_t st, int *occ)
 {
-    if (kmax <= 4) return launch_k<L, MIXED, 4, NPMAX>(a, blocks, lds, st);
-    return launch_k<L, MIXED, 8, NPMAX>(a, blocks, lds, st);
+    if (kmax <= 4) return launch_k<L, MIXED, 4, NPMAX>(a, blocks, lds, st, occ);
+    return launch_k<L, MIXED, 8, NPMAX>(a, blocks, lds, st, occ);
 }
 
 // a single lane-count class NP: only its code, and a tighter term bound
 template <int L, bool MIXED, int NP>
-static int launch_1(const TrackArgs &a, int kmax, int blocks, size_t lds, hipStream_t st)
+static int launch_1(const TrackArgs &a, int kmax, int blocks, size_t lds, hipStream_t st, int *occ)
 {
-    if (kmax <= 2) return launch_k<L, MIXED, 2, -NP>(a, blocks, lds, st);
-    if (kmax <= 4) return launch_k<L, MIXED, 4, -NP>(a, blocks, lds, st);
-    return launch_k<L, MIXED, 8, -NP>(a, blocks, lds, st);
+    if (kmax <= 2) return launch_k<L, MIXED, 2, -NP>(a, blocks, lds, st, occ);
+    if (kmax <= 4) return launch_k<L, MIXED, 4, -NP>(a, blocks, lds, st, occ);
+    return launch_k<L, MIXED, 8, -NP>(a, blocks, lds, st, occ);
 }
 
 template <int L, bool MIXED>
-int track_launch_t(const TrackArgs &a, int kmax, int blocks, size_t lds, hipStream_t st)
+int track_launch_t(const TrackArgs &a, int kmax, int blocks, size_t lds, hipStream_t st, int *occ)
 {
     int npmax = 4, classes = 0;
     for (int c = 0; c < 4; ++c)
@@ -44,15 +51,15 @@ int track_launch_t(const TrackArgs &a, int kmax, int blocks, size_t lds, hipStre
         }
     if (classes == 1) {
         switch (npmax) {
-        case 4: return launch_1<L, MIXED, 4>(a, kmax, blocks, lds, st);
-        case 8: return launch_1<L, MIXED, 8>(a, kmax, blocks, lds, st);
-        case 16: return launch_1<L, MIXED, 16>(a, kmax, blocks, lds, st);
-        default: return launch_1<L, MIXED, 32>(a, kmax, blocks, lds, st);
+        case 4: return launch_1<L, MIXED, 4>(a, kmax, blocks, lds, st, occ);
+        case 8: return launch_1<L, MIXED, 8>(a, kmax, blocks, lds, st, occ);
+        case 16: return launch_1<L, MIXED, 16>(a, kmax, blocks, lds, st, occ);
+        default: return launch_1<L, MIXED, 32>(a, kmax, blocks, lds, st, occ);
         }
     }
-    if (npmax <= 8) return launch_n<L, MIXED, 8>(a, kmax, blocks, lds, st);
-    if (npmax <= 16) return launch_n<L, MIXED, 16>(a, kmax, blocks, lds, st);
-    return launch_n<L, MIXED, 32>(a, kmax, blocks, lds, st);
+    if (npmax <= 8) return launch_n<L, MIXED, 8>(a, kmax, blocks, lds, st, occ);
+    if (npmax <= 16) return launch_n<L, MIXED, 16>(a, kmax, blocks, lds, st, occ);
+    return launch_n<L, MIXED, 32>(a, kmax, blocks, lds, st, occ);
 }
 
 template <int L>
@@ -72,7 +79,7 @@ int slot_init_launch_t(void *state, int64_t nslots, hipStream_t st)
 }
 
 #define PH_TRACK_INSTANTIATE(L_, M_)                                                             \
-    template int track_launch_t<L_, M_>(const TrackArgs &, int, int, size_t, hipStream_t);
+    template int track_launch_t<L_, M_>(const TrackArgs &, int, int, size_t, hipStream_t, int *);
 
 #define PH_SLOT_INSTANTIATE(L_)                                                                  \
     template size_t slot_bytes_t<L_>();                                                          \

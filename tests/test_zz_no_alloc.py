@@ -85,8 +85,8 @@ def test_noalloc_rejections():
     with pytest.raises(ph.PHError, match="not prepared"):
         ph.track_noalloc(S, gam, 8, ph.track_opts(prec=1), x_start=ph.to_soa(X0), start=G)
     # a predictor history larger than the scratch: 65536 paths of n = 16 at
-    # 16 workgroups per CU is 4096 workgroups of 64 QD slots (50 MB); refused
-    # before any launch
+    # as many workgroups as fit the CUs (7 per CU on the MI355X: 1792
+    # workgroups of 64 QD slots, 22 MB); refused before any launch
     q = synth.tracking_quadratic16()
     Q = ph.System(q)
     o3 = ph.track_opts(prec=4, mixed=1, predictor_order=4)
