@@ -55,16 +55,16 @@ TRAFFIC = {
     # the accumulation-register kernels stage x once per (point tile,
     # equation group): their reads depend on the tiling
     "eval_dd_arow_kernel": {
-        "bytes": 81638548 + 2214672256,
-        "launch": (3, 4, 1),
+        "by_launch": {(3, 4, 1): 82959659 + 2214743040, (3, 4, 2): 147431253 + 2214706944,
+                      (3, 4, 4): 281445760 + 2214725888},
         "sources": {"paper_1505_00383_amd/csrc/eval_dd.hip": "4f9b4854ab9300ef",
                     "paper_1505_00383_amd/csrc/ph_arow.hpp": "aee6853f608672f7",
                     "paper_1505_00383_amd/csrc/ph_arith.hpp": "1f4274c3666f77a9",
                     "paper_1505_00383_amd/csrc/ph_internal.hpp": "9c1cfcc941ec5fea"},
     },
     "eval_qd_arow_kernel": {
-        "bytes": 557253861 + 4429192960,
-        "launch": (3, 4, 4),
+        "by_launch": {(3, 4, 1): 173766528 + 4429209643, (3, 4, 2): 299420373 + 4429190229,
+                      (3, 4, 4): 559601621 + 4429190101},
         "sources": {"paper_1505_00383_amd/csrc/eval_qd.hip": "218895931cd72bc2",
                     "paper_1505_00383_amd/csrc/ph_arow.hpp": "aee6853f608672f7",
                     "paper_1505_00383_amd/csrc/ph_arith.hpp": "1f4274c3666f77a9",
@@ -82,13 +82,13 @@ def traffic_of(kernel, launch=None):
         # these kernels run at most four waves per workgroup (one per SIMD):
         # a larger configured count launches four
         launch = (launch[0], min(launch[1], 4), launch[2])
-    if "launch" in t and (launch is None or tuple(launch) != t["launch"]):
+    if "by_launch" in t and (launch is None or tuple(launch) not in t["by_launch"]):
         return None
     for path, sha in t["sources"].items():
         with open(os.path.join(ROOT, path), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest()[:16] != sha:
                 return None
-    return t["bytes"]
+    return t["by_launch"][tuple(launch)] if "by_launch" in t else t["bytes"]
 
 
 def flops_per_point(sysm, L):
@@ -665,6 +665,10 @@ def main():
     ap.add_argument("--kernel", type=int, default=0,
                     help="evaluation kernel choice of ph_eval_set_config for the timed launches "
                          "(0 automatic; 5 the unfused three-kernel design)")
+    ap.add_argument("--waves", type=int, default=0,
+                    help="with --kernel: waves per workgroup (0: the library's default)")
+    ap.add_argument("--groups", type=int, default=0,
+                    help="with --kernel: equation groups (0: the library's default)")
     ap.add_argument("--mode", default="eval",
                     choices=["eval", "eval_hbm", "track_n8_dd", "track_n16_qd", "track_batch", "copy"],
                     help="eval: the benchmark line; the others run one workload for profiling: "
@@ -699,7 +703,7 @@ def main():
     # timed launches, with no idle gap (its clock drops when it idles)
     x0, t0 = synth.torus_points(sysm, npts, L)
     if args.kernel:
-        ph.eval_set_config(S, L, args.kernel)
+        ph.eval_set_config(S, L, args.kernel, args.waves, args.groups)
         if args.kernel == ph.EVAL_UNFUSED:
             ph.eval_prepare(S, L, unfused_points=npts)
     elif not args.no_autotune:

@@ -53,20 +53,21 @@ def test_traffic_guard(monkeypatch):
     with open(os.path.join(ROOT, path), "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()[:16]
     table = {"k_any": {"bytes": 123, "sources": {path: sha}},
-             "k_tiled": {"bytes": 456, "launch": (1, 8, 4), "sources": {path: sha}},
+             "k_tiled": {"by_launch": {(1, 8, 4): 456, (1, 8, 1): 321}, "sources": {path: sha}},
              "k_stale": {"bytes": 789, "sources": {path: "0" * 16}}}
     monkeypatch.setattr(bench, "TRAFFIC", table)
     assert bench.traffic_of("k_any") == 123
     assert bench.traffic_of("k_any", (3, 2, 1)) == 123
     assert bench.traffic_of("k_tiled", (1, 8, 4)) == 456
     assert bench.traffic_of("k_tiled", [1, 8, 4]) == 456
+    assert bench.traffic_of("k_tiled", (1, 8, 1)) == 321
     assert bench.traffic_of("k_tiled", (1, 8, 2)) is None
     assert bench.traffic_of("k_tiled") is None
     assert bench.traffic_of("k_stale") is None
     assert bench.traffic_of("unknown") is None
     # the accumulation-register kernels launch at most four waves per
     # workgroup: a larger configured count is the same launch
-    monkeypatch.setattr(bench, "TRAFFIC", {"eval_dd_arow_kernel": {"bytes": 7, "launch": (3, 4, 1),
+    monkeypatch.setattr(bench, "TRAFFIC", {"eval_dd_arow_kernel": {"by_launch": {(3, 4, 1): 7},
                                                                    "sources": {path: sha}}})
     assert bench.traffic_of("eval_dd_arow_kernel", (3, 8, 1)) == 7
     assert bench.traffic_of("eval_dd_arow_kernel", (3, 6, 1)) == 7
