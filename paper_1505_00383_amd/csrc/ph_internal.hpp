@@ -94,6 +94,7 @@ struct DevTable {
     int32_t *eq_off = nullptr;   // [n_eq + 1]
     int4 *tdesc = nullptr;       // [n_terms]
     uint32_t *fac = nullptr;     // [n_fac]
+    uint32_t *fac8 = nullptr;    // [n_terms][8]: each term's factor words, zero padded (tracker)
     double *coef = nullptr;      // [n_terms][2][4] limbs
     int32_t *zc_off = nullptr;   // [n_eq + 1] columns of each row no term touches
     int32_t *zc = nullptr;

@@ -14,6 +14,7 @@ struct SysDesc {
     const int32_t *eq_off;   // merged term table: target terms, then start terms
     const int4 *tdesc;
     const uint32_t *fac;
+    const uint32_t *fac8;    // [term][8] factor words by term index
     const double *coef;
     const int64_t *path_ids; // multi-index number of every tracked path, or NULL (0..npaths-1)
     int64_t path_off;        // first global path index of this system (outputs)

@@ -430,23 +430,44 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
                 lds_put<LS>(en, c_add<LS>(lds_get<LS>(en), part));
             };
             const int s0 = sd.eq_off[eq], s1 = sd.eq_off[eq + 1];
+            // a term's descriptor, coefficient and factor words (eight
+            // slots per term, addressed by the term index alone) load
+            // together; up to double double the lane reads its next term
+            // while it sweeps the current one (quad double has no registers
+            // to spare for that)
+            constexpr bool AHEAD = L <= 2;
+            auto fetch = [&](int s, int4 &d, C<L> &c, uint32_t (&fw)[KMAX]) {
+                d = sd.tdesc[s];
+#pragma unroll
+                for (int l = 0; l < L; ++l) {
+                    c.re.v[l] = sd.coef[(int64_t)s * 8 + l];
+                    c.im.v[l] = sd.coef[(int64_t)s * 8 + 4 + l];
+                }
+#pragma unroll
+                for (int l = 0; l < KMAX; ++l) fw[l] = sd.fac8[(int64_t)s * 8 + l];
+            };
+            int4 dn = {0, 0, 0, 0};
+            C<L> cn = c_zero<L>();
+            uint32_t fn[KMAX];
+#pragma unroll
+            for (int l = 0; l < KMAX; ++l) fn[l] = 0u;
+            if (AHEAD && s0 + sr < s1) fetch(s0 + sr, dn, cn, fn);
             for (int sb = s0; sb < s1; sb += nsh) {
                 const int s = sb + sr;
-                if (s < s1) {
-                    const int4 d = sd.tdesc[s];
-                    C<L> c;
+                int4 d = dn;
+                C<L> c = cn;
+                uint32_t fw[KMAX];
 #pragma unroll
-                    for (int l = 0; l < L; ++l) {
-                        c.re.v[l] = sd.coef[(int64_t)s * 8 + l];
-                        c.im.v[l] = sd.coef[(int64_t)s * 8 + 4 + l];
-                    }
+                for (int l = 0; l < KMAX; ++l) fw[l] = fn[l];
+                if (AHEAD) {
+                    if (s + nsh < s1) fetch(s + nsh, dn, cn, fn);
+                } else if (s < s1) {
+                    fetch(s, d, c, fw);
+                }
+                if (s < s1) {
                     c = d.z ? c_mul<L>(c, gs) : c_mul_d<L>(c, tt);
                     C<L> tv = c;
                     if (d.x > 0) {
-                        uint32_t fw[KMAX];
-#pragma unroll
-                        for (int l = 0; l < KMAX; ++l)
-                            if (l < d.x) fw[l] = sd.fac[d.y + l];
                         tv = term_sweep<KMAX, true, (L == 1)>(
                             d.x, fw, c, X, [&](int l, uint32_t w, const C<L> &part) {
                                 const C<LS> pn = narrow<LS, L>(part);
@@ -488,7 +509,7 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
                                     pn.re.v[z] = *slot(hrow, 2 * L + l * 2 * LS + z);
                                     pn.im.v[z] = *slot(hrow, 2 * L + l * 2 * LS + LS + z);
                                 }
-                                add_part(sd.fac[d.y + l], pn);
+                                add_part(sd.fac8[(int64_t)(sb + q) * 8 + l], pn);
                             }
                             C<L> tv;
 #pragma unroll

@@ -256,6 +256,12 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
     }
     if (fac.empty()) fac.push_back(0);
     if (zc.empty()) zc.push_back(0);
+    // the tracker's copy of the factor words: eight slots per term (zeros
+    // past its factors), so that a term's words are addressed by its index
+    // alone and can be read together with its descriptor
+    std::vector<uint32_t> fac8(tdesc.size() * 8, 0u);
+    for (size_t tt = 0; tt < tdesc.size(); ++tt)
+        for (int l = 0; l < tdesc[tt].x && l < 8; ++l) fac8[tt * 8 + l] = fac[tdesc[tt].y + l];
 
     size_t o_eq = 0;
     size_t o_td = o_eq + align256(eq_off.size() * 4);
@@ -271,7 +277,8 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
     size_t o_us = o_dr + align256(d_run.size() * 4);
     size_t o_uo = o_us + align256(u_slot.size() * 4);
     size_t o_ul = o_uo + align256(u_off.size() * 4);
-    size_t total = o_ul + align256(u_list.size() * 4);
+    size_t o_f8 = o_ul + align256(u_list.size() * 4);
+    size_t total = o_f8 + align256(fac8.size() * 4);
     std::vector<char> host(total, 0);
     std::memcpy(host.data() + o_eq, eq_off.data(), eq_off.size() * 4);
     std::memcpy(host.data() + o_td, tdesc.data(), tdesc.size() * sizeof(int4));
@@ -287,6 +294,7 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
     std::memcpy(host.data() + o_us, u_slot.data(), u_slot.size() * 4);
     std::memcpy(host.data() + o_uo, u_off.data(), u_off.size() * 4);
     std::memcpy(host.data() + o_ul, u_list.data(), u_list.size() * 4);
+    std::memcpy(host.data() + o_f8, fac8.data(), fac8.size() * 4);
     char *dev = nullptr;
     PH_HIP(hipMalloc(&dev, total));
     hipError_t e = hipMemcpy(dev, host.data(), total, hipMemcpyHostToDevice);
@@ -303,6 +311,7 @@ int build_table(const HostSystem &f, const HostSystem *g, DevTable &out)
     out.eq_off = reinterpret_cast<int32_t *>(dev + o_eq);
     out.tdesc = reinterpret_cast<int4 *>(dev + o_td);
     out.fac = reinterpret_cast<uint32_t *>(dev + o_fac);
+    out.fac8 = reinterpret_cast<uint32_t *>(dev + o_f8);
     out.coef = reinterpret_cast<double *>(dev + o_cf);
     out.zc_off = reinterpret_cast<int32_t *>(dev + o_zo);
     out.zc = reinterpret_cast<int32_t *>(dev + o_zc);

@@ -225,6 +225,7 @@ static int track_impl(int nsys, const ph_system *const *targets, const ph_system
             d.eq_off = tab->eq_off;
             d.tdesc = tab->tdesc;
             d.fac = tab->fac;
+            d.fac8 = tab->fac8;
             d.coef = tab->coef;
             d.path_off = path_off[s];
             d.npaths = path_off[s + 1] - path_off[s];
