@@ -46,29 +46,29 @@ PREC_NAME = {1: "complex double", 2: "complex double double", 4: "complex quad d
 TRAFFIC = {
     # the double kernel writes H and J once whatever its tiling
     "eval_d_pinned_kernel": {
-        "bytes": 41922859 + 1107428309,   # read + write
+        "bytes": 41826688 + 1107419605,   # read + write
         "sources": {"paper_1505_00383_amd/csrc/eval.hip": "65189039477730cf",
                     "paper_1505_00383_amd/csrc/ph_arith.hpp": "1f4274c3666f77a9",
                     "paper_1505_00383_amd/csrc/ph_sweep.hpp": "afaab2dda7ee3e60",
-                    "paper_1505_00383_amd/csrc/ph_internal.hpp": "9c1cfcc941ec5fea"},
+                    "paper_1505_00383_amd/csrc/ph_internal.hpp": "ab9104fb80a39058"},
     },
     # the accumulation-register kernels stage x once per (point tile,
     # equation group): their reads depend on the tiling
     "eval_dd_arow_kernel": {
-        "by_launch": {(3, 4, 1): 82959659 + 2214743040, (3, 4, 2): 147431253 + 2214706944,
-                      (3, 4, 4): 281445760 + 2214725888},
+        "by_launch": {(3, 4, 1): 82423040 + 2214619008, (3, 4, 2): 147354795 + 2214631893,
+                      (3, 4, 4): 281448320 + 2214658347},
         "sources": {"paper_1505_00383_amd/csrc/eval_dd.hip": "4f9b4854ab9300ef",
                     "paper_1505_00383_amd/csrc/ph_arow.hpp": "aee6853f608672f7",
                     "paper_1505_00383_amd/csrc/ph_arith.hpp": "1f4274c3666f77a9",
-                    "paper_1505_00383_amd/csrc/ph_internal.hpp": "9c1cfcc941ec5fea"},
+                    "paper_1505_00383_amd/csrc/ph_internal.hpp": "ab9104fb80a39058"},
     },
     "eval_qd_arow_kernel": {
-        "by_launch": {(3, 4, 1): 173766528 + 4429209643, (3, 4, 2): 299420373 + 4429190229,
-                      (3, 4, 4): 559601621 + 4429190101},
+        "by_launch": {(3, 4, 1): 169237333 + 4429185621, (3, 4, 2): 296473472 + 4429185579,
+                      (3, 4, 4): 557277269 + 4429185493},
         "sources": {"paper_1505_00383_amd/csrc/eval_qd.hip": "218895931cd72bc2",
                     "paper_1505_00383_amd/csrc/ph_arow.hpp": "aee6853f608672f7",
                     "paper_1505_00383_amd/csrc/ph_arith.hpp": "1f4274c3666f77a9",
-                    "paper_1505_00383_amd/csrc/ph_internal.hpp": "9c1cfcc941ec5fea"},
+                    "paper_1505_00383_amd/csrc/ph_internal.hpp": "ab9104fb80a39058"},
     },
 }
 
