@@ -298,6 +298,15 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
 
     bool retired = false;
     const long long t_start = a.budget ? wall_clock64() : 0;  // time-budgeted launches
+    // what the evaluation reads of the slot's system, kept across rounds and
+    // read again only when the slot moves to another system: the term-table
+    // pointers, gamma, and this lane's equation and term range
+    int k_sidx = -1, k_n = -1;
+    const int4 *k_tdesc = nullptr;
+    const double *k_coef = nullptr;
+    const uint32_t *k_fac8 = nullptr;
+    double k_gre = 0.0, k_gim = 0.0;
+    int k_sub = NP, k_s0 = 0, k_s1 = 0;
     for (int round = 0; round < max_rounds; ++round) {
         // ---- refill: pop a path from the device queue of this class -------
         if (phase == PH_EMPTY) {
@@ -381,7 +390,24 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
         }
         const bool busy = phase == PH_CORRECT || phase == PH_POLISH;
         const double tt = phase == PH_POLISH ? 1.0 : t1;
-        const SysDesc &sd = a.sys[sidx];
+        if (busy && (sidx != k_sidx || n != k_n)) {
+            const SysDesc &sd = a.sys[sidx];
+            k_tdesc = sd.tdesc;
+            k_coef = sd.coef;
+            k_fac8 = sd.fac8;
+            k_gre = sd.gre;
+            k_gim = sd.gim;
+            int sb4 = 4;
+            while (sb4 < n) sb4 *= 2;
+            // a helper's row holds 2L + kmax 2LS doubles of hand-over
+            if (sb4 > NP || 2 * L + sd.kmax * 2 * LS > (NP + 1) * 2 * LS) sb4 = NP;
+            k_sub = sb4;
+            const int e = i % sb4;
+            k_s0 = e < n ? sd.eq_off[e] : 0;
+            k_s1 = e < n ? sd.eq_off[e + 1] : 0;
+            k_sidx = sidx;
+            k_n = n;
+        }
 
         // ---- evaluate H and J at (xh, tt) ----------------------------------
         // sub = the smallest power of two >= n (at least 4); with nsh = NP / sub
@@ -401,10 +427,7 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        int sub = 4;
-        while (sub < n) sub *= 2;
-        // a helper's row holds 2L + kmax 2LS doubles of hand-over
-        if (sub > NP || 2 * L + sd.kmax * 2 * LS > (NP + 1) * 2 * LS) sub = NP;
+        const int sub = k_sub;
         const int nsh = NP / sub, eq = i % sub, sr = i / sub;
         // m-th double of row `row` of the group's matrix (hand-over slots)
         auto slot = [&](int row, int m) -> double * { return W(m / (2 * LS), row) + m % (2 * LS); };
@@ -415,7 +438,7 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
             R<L> omt = r_zero<L>();
             omt.v[0] = o1;
             if constexpr (L > 1) omt.v[1] = oe;
-            const C<L> gs = c_mul_r<L>(c_from<L>(sd.gre, sd.gim), omt);
+            const C<L> gs = c_mul_r<L>(c_from<L>(k_gre, k_gim), omt);
             auto X = [&](int var) -> C<L> {
                 C<L> z;
 #pragma unroll
@@ -429,7 +452,7 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
                 double *en = W(fac_var(w), eq);
                 lds_put<LS>(en, c_add<LS>(lds_get<LS>(en), part));
             };
-            const int s0 = sd.eq_off[eq], s1 = sd.eq_off[eq + 1];
+            const int s0 = k_s0, s1 = k_s1;
             // a term's descriptor, coefficient and factor words (eight
             // slots per term, addressed by the term index alone) load
             // together; up to double double the lane reads its next term
@@ -437,14 +460,14 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
             // to spare for that)
             constexpr bool AHEAD = L <= 2;
             auto fetch = [&](int s, int4 &d, C<L> &c, uint32_t (&fw)[KMAX]) {
-                d = sd.tdesc[s];
+                d = k_tdesc[s];
 #pragma unroll
                 for (int l = 0; l < L; ++l) {
-                    c.re.v[l] = sd.coef[(int64_t)s * 8 + l];
-                    c.im.v[l] = sd.coef[(int64_t)s * 8 + 4 + l];
+                    c.re.v[l] = k_coef[(int64_t)s * 8 + l];
+                    c.im.v[l] = k_coef[(int64_t)s * 8 + 4 + l];
                 }
 #pragma unroll
-                for (int l = 0; l < KMAX; ++l) fw[l] = sd.fac8[(int64_t)s * 8 + l];
+                for (int l = 0; l < KMAX; ++l) fw[l] = k_fac8[(int64_t)s * 8 + l];
             };
             int4 dn = {0, 0, 0, 0};
             C<L> cn = c_zero<L>();
@@ -501,7 +524,7 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
                         // order the sweep issues them (last factor first)
                         for (int q = 1; q < nsh && sb + q < s1; ++q) {
                             const int hrow = i + q * sub;
-                            const int4 d = sd.tdesc[sb + q];
+                            const int4 d = k_tdesc[sb + q];
                             for (int l = d.x - 1; l >= 0; --l) {
                                 C<LS> pn;
 #pragma unroll
@@ -509,7 +532,7 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
                                     pn.re.v[z] = *slot(hrow, 2 * L + l * 2 * LS + z);
                                     pn.im.v[z] = *slot(hrow, 2 * L + l * 2 * LS + LS + z);
                                 }
-                                add_part(sd.fac8[(int64_t)(sb + q) * 8 + l], pn);
+                                add_part(k_fac8[(int64_t)(sb + q) * 8 + l], pn);
                             }
                             C<L> tv;
 #pragma unroll
