@@ -491,7 +491,7 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
                     c = d.z ? c_mul<L>(c, gs) : c_mul_d<L>(c, tt);
                     C<L> tv = c;
                     if (d.x > 0) {
-                        tv = term_sweep<KMAX, true, (L == 1)>(
+                        tv = term_sweep<KMAX, true, (L <= 2)>(
                             d.x, fw, c, X, [&](int l, uint32_t w, const C<L> &part) {
                                 const C<LS> pn = narrow<LS, L>(part);
                                 if (sr == 0) {
