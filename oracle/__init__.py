@@ -24,7 +24,8 @@ Parity status of every exported function (what pins it, in ``tests/``):
   (<= 256 u_L S, L = 1, 2, 4), mixed vs plain agreement (1e-24 DD, 1e-48 QD),
   endpoints independent of the start system, the residual half of the
   convergence test, the endpoint check after the polish, forced failures.
-  The step sequence itself is parity unpinned (only endpoints are pinned).
+  The step sequence itself is pinned only on f = g (a hand-derived step count);
+  on moving paths it is parity unpinned (only endpoints are pinned).
 """
 from __future__ import annotations
 

@@ -4,7 +4,8 @@ Endpoint parity: ||x_gpu - x_ref||_inf / max(1, ||x_ref||_inf) <= 1e-8
 after polishing, where x_ref is the oracle's PLAIN track at the same precision.
 When the two disagree on a path, the oracle re-tracks it with h_max / 10; the GPU
 endpoint must then agree with the re-track (the other one jumped paths).
-The step sequence is parity-unpinned: step counts are compared statistically.
+The step sequence is pinned on f = g only (its hand-derived count); elsewhere
+step counts are compared statistically.
 """
 import os
 
@@ -480,3 +481,31 @@ def test_residual_test_and_endpoint_check_on_gpu():
     assert abs(ph.from_soa(r1["x_end"], 1, (1, 2, 1))[0, 0, 0, 0] - 2.0) <= 1e-14
     r2 = ph.track(F, gamma, 1, ph.track_opts(**loose, diverge_norm=1.9))
     assert r2["status"][0] == -1 and ph.REASONS[int(r2["reason"][0])] == "DIVERGED"
+
+
+@pytest.mark.parametrize("L,mixed", [(1, 0), (2, 1), (4, 0)])
+def test_f_equals_g_step_sequence_by_hand_gpu(L, mixed):
+    """f = g: every path stays at its start point, every step is accepted
+    with one Newton step, and the step count is the hand-derived one of
+    tests/golden/step_sequence_f_equals_g.txt on both schedules."""
+    want = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "step_sequence_f_equals_g.txt")) as f:
+        for ln in f:
+            if ln.strip() and not ln.startswith("#"):
+                k, v = ln.split()
+                want[k] = int(v)
+    n, deg = 3, [2, 3, 2]
+    s = synth.system_from_terms(n, [[(1, {i: deg[i]}), (-1, {})] for i in range(n)])
+    gamma = complex(np.cos(1.1), np.sin(1.1))
+    S = ph.System(s)
+    for sched in (ph.SCHED_PERSISTENT, ph.SCHED_GRAPH):
+        print(f"[gpu] f = g step count L={L} mixed={mixed} schedule={sched}", flush=True)
+        res = ph.track(S, gamma, 12, ph.track_opts(prec=L, mixed=mixed, schedule=sched))
+        assert np.all(res["status"] == 1)
+        assert np.all(res["steps"] == want["steps"]), res["steps"]
+        assert res["report"]["rejected"] == 0
+        assert res["report"]["newton_its"] == 12 * want["newton"]
+        x = _x_end(res, n, L, 12)
+        for p in range(12):
+            x0 = oracle.start_solution(L, np.array(deg, dtype=np.int32), p)
+            assert np.max(np.abs(x[p].sum(-1) - np.asarray(x0).reshape(n, 2, L).sum(-1))) <= 1e-14

@@ -14,6 +14,8 @@ Only endpoints are pinned (the step sequence is a heuristic and parity-unpinned)
 """
 from fractions import Fraction
 
+import os
+
 import numpy as np
 import pytest
 
@@ -69,6 +71,33 @@ def test_f_equals_g_paths_stay_put(L):
     for p in range(12):
         x0 = oracle.start_solution(L, np.array(deg, dtype=np.int32), p)
         assert np.max(np.abs(_cx(r["x"][p]) - _cx(x0))) <= 1e-14
+
+
+def _golden(name):
+    out = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+        for ln in f:
+            if ln.strip() and not ln.startswith("#"):
+                k, v = ln.split()
+                out[k] = int(v)
+    return out
+
+
+@pytest.mark.parametrize("L", [1, 2, 4])
+def test_f_equals_g_step_sequence_by_hand(L):
+    """On f = g every step is accepted with one Newton step, so the step count
+    is what the step-size rule gives by hand (tests/golden/
+    step_sequence_f_equals_g.txt): a wrong expansion count, factor or cap, or
+    a rejected step, changes it."""
+    want = _golden("step_sequence_f_equals_g.txt")
+    n = 3
+    deg = [2, 3, 2]
+    s = synth.system_from_terms(n, [[(1, {i: deg[i]}), (-1, {})] for i in range(n)])
+    gamma = complex(np.cos(1.1), np.sin(1.1))
+    r = oracle.track(s, gamma, range(4), oracle.Opts(prec=L))
+    assert np.all(r["status"] == 1)
+    assert np.all(r["steps"] == want["steps"])
+    assert np.all(r["newton"] == want["newton"])
 
 
 def _branch_endpoint(gamma, c, d, x0, steps=20000):
