@@ -224,6 +224,30 @@ def test_graph_schedule_matches_persistent_bitwise():
         assert a["report"]["newton_its"] == r["report"]["newton_its"]
 
 
+def test_more_workgroups_asked_than_fit_a_cu():
+    """16384 paths of the n = 16 system need 4096 workgroups: more than the
+    CUs hold at once even at the default 8 per CU.  Asked for 64 per CU, the
+    launch is capped at what the kernel fits on a CU, so every workgroup of a
+    round launch starts with it; both schedules give bitwise the same
+    endpoints, status and step counts as the default launch."""
+    s = synth.tracking_quadratic16()
+    g = synth.gamma_of(s)
+    S = ph.System(s)
+    base = ph.track_opts(prec=2, mixed=1)
+    print("[gpu] 16384 paths, 64 workgroups per CU asked", flush=True)
+    a = ph.track(S, g, 16384, base)
+    b = ph.track(S, g, 16384, ph.track_opts(prec=2, mixed=1, blocks_per_cu=64))
+    c = ph.track(S, g, 16384, ph.track_opts(prec=2, mixed=1, blocks_per_cu=64, schedule=ph.SCHED_GRAPH,
+                                            launch_ms=1.0))
+    print(f"[gpu] default {a['report']['seconds']:.3f}s persistent-64 {b['report']['seconds']:.3f}s "
+          f"graph-64 {c['report']['seconds']:.3f}s", flush=True)
+    assert np.sum(a["status"] == 1) > 16000
+    for r in (b, c):
+        assert np.array_equal(a["x_end"].cpu().numpy(), r["x_end"].cpu().numpy())
+        for k in ("status", "reason", "steps"):
+            assert np.array_equal(a[k], r[k])
+
+
 @pytest.mark.parametrize("schedule", [0, 1])
 def test_batch_lane_classes(schedule):
     """Systems of n = 3, 6, 12 (4, 8 and 16 lanes per path) in one launch."""
