@@ -450,7 +450,17 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
             };
             auto add_part = [&](uint32_t w, const C<LS> &part) {
                 double *en = W(fac_var(w), eq);
-                lds_put<LS>(en, c_add<LS>(lds_get<LS>(en), part));
+                if constexpr (LS == 1) {
+                    // FP64 entries: LDS atomic adds, which the lane issues
+                    // without waiting for a read of the entry.  The lane is
+                    // the only writer of its row and its LDS operations
+                    // complete in order, so the sums are the same additions
+                    // in the same order as a read, an add and a write.
+                    __hip_atomic_fetch_add(en, part.re.v[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_fetch_add(en + 1, part.im.v[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                } else {
+                    lds_put<LS>(en, c_add<LS>(lds_get<LS>(en), part));
+                }
             };
             const int s0 = k_s0, s1 = k_s1;
             // a term's descriptor, coefficient and factor words (eight
