@@ -587,11 +587,32 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
             {  // group-uniform
                 C<LS> wk = lds_get<LS>(W(k, i));
                 R<LS> nr = gsum_r<NP, LS>(c_abs2<LS>(wk));
-                R<LS> rkk = r_sqrt<LS>(nr);
+                R<LS> rkk, inv;
+                if constexpr (LS == 1) {
+                    // FP64: the norm and its reciprocal from one reciprocal
+                    // square root refined by two coupled Newton steps
+                    // (Goldschmidt: g -> sqrt(x), h -> 1 / (2 sqrt(x))), in
+                    // place of a square root and a division in series
+                    const double x = nr.v[0];
+                    const double y = __builtin_amdgcn_rsq(x);
+                    double g = x * y, h = 0.5 * y;
+#pragma unroll
+                    for (int it = 0; it < 2; ++it) {
+                        const double r = __builtin_fma(-g, h, 0.5);
+                        g = __builtin_fma(g, r, g);
+                        h = __builtin_fma(h, r, h);
+                    }
+                    // a norm below the normal range, zero or NaN counts as zero
+                    // (singular), infinity stays NaN (singular as well)
+                    rkk.v[0] = x >= 0x1p-1022 ? g : 0.0;
+                    inv.v[0] = 2.0 * h;
+                } else {
+                    rkk = r_sqrt<LS>(nr);
+                }
                 if (!(rkk.v[0] > a.eps_sing * fro)) sing = true;
                 if (sing) break;
                 {
-                    R<LS> inv = r_div<LS>(r_from<LS>(1.0), rkk);
+                    if constexpr (LS != 1) inv = r_div<LS>(r_from<LS>(1.0), rkk);
                     C<LS> q = c_mul_r<LS>(wk, inv);
                     // projection of column j on q: r = q^H w_j (group sum),
                     // w_j -= r q; column k is dead after step k, so R(k, j)
