@@ -96,6 +96,35 @@ __device__ __forceinline__ C<L> shfl_c(C<L> v, int src)
     return r;
 }
 
+// The value of the one lane of each group for which `mine` holds, in every
+// lane of the group: the others contribute zero bits and the group ORs the
+// bit patterns with the reduction's partner moves (DPP within a 16-lane
+// row), so the value arrives bit for bit without a trip through LDS.
+template <int NP, int O = 1>
+__device__ __forceinline__ unsigned long long gbcast_bits(unsigned long long b)
+{
+    if constexpr (O < NP) {
+        const double p = red_partner<O>(__builtin_bit_cast(double, b));
+        return gbcast_bits<NP, 2 * O>(b | __builtin_bit_cast(unsigned long long, p));
+    } else {
+        return b;
+    }
+}
+
+template <int NP, int L>
+__device__ __forceinline__ C<L> gbcast_c(C<L> v, bool mine)
+{
+    C<L> r;
+#pragma unroll
+    for (int l = 0; l < L; ++l) {
+        const unsigned long long br = mine ? __builtin_bit_cast(unsigned long long, v.re.v[l]) : 0ull;
+        const unsigned long long bi = mine ? __builtin_bit_cast(unsigned long long, v.im.v[l]) : 0ull;
+        r.re.v[l] = __builtin_bit_cast(double, gbcast_bits<NP>(br));
+        r.im.v[l] = __builtin_bit_cast(double, gbcast_bits<NP>(bi));
+    }
+    return r;
+}
+
 template <int L>
 __device__ __forceinline__ double c_absd(C<L> a)
 {
@@ -673,7 +702,10 @@ __device__ __forceinline__ bool run_rounds(const TrackArgs &a, const TrackClass 
                     dk = c_mul_r<LS>(acc, inv_i);
                     dxi = dk;
                 }
-                dk = shfl_c<LS>(dk, base + k);
+                if constexpr (NP <= 16)
+                    dk = gbcast_c<NP, LS>(dk, i == k);
+                else
+                    dk = shfl_c<LS>(dk, base + k);
                 if (i < k) {
                     C<LS> rik = lds_get<LS>(W(i, k));  // R(i, k), stored in column i, row k
                     acc = c_sub<LS>(acc, c_mul<LS>(rik, dk));
