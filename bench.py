@@ -250,8 +250,34 @@ def time_track(ph, torch, sysm, L, mixed, npaths, reps=1, order=1):
                 k: int(rep[k]) for k in ("n_diverged", "n_step_underflow", "n_max_steps",
                                          "n_singular", "n_nan")},
             "steps_per_path": rep["steps"] / max(npaths, 1),
+            "steps_p50_p99_max": [float(np.percentile(res["steps"], 50)),
+                                  float(np.percentile(res["steps"], 99)), int(res["steps"].max())],
             "newton_per_path": rep["newton_its"] / max(npaths, 1),
             "roofline": track_roofline(sysm, L, mixed, order, rep, sec, npaths)}, res
+
+
+def longest_path_alone(ph, torch, sysm, L, mixed, res, whole_s, reps=2):
+    """The path with the most steps in ``res``, tracked by itself from its own
+    start point: when this takes nearly as long as the whole run, paths/s on
+    that workload is set by one path's step latency, not by throughput."""
+    from paper_1505_00383_amd import synth
+    S = ph.System(sysm)
+    g = synth.gamma_of(sysm)
+    opts = ph.track_opts(prec=L, mixed=mixed)
+    i = int(np.argmax(res["steps"]))
+    xs = ph.start_solutions(S, L, i, 1)
+    st = torch.cuda.current_stream()
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        r1 = ph.track(S, g, 1, opts, x_start=xs)
+        e1.record(st)
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3
+        best = sec if best is None else min(best, sec)
+    return {"path": i, "steps": int(r1["steps"][0]), "seconds": best,
+            "fraction_of_whole_run": best / whole_s}
 
 
 def _limb_err(xg, xr):
@@ -571,7 +597,9 @@ def tracking_extras(ph, torch, cpu=True):
     B = 3 ** 8
     dd_m, r_m = time_track(ph, torch, cub, 2, 1, B, reps=2)
     dd_p, r_p = time_track(ph, torch, cub, 2, 0, B, reps=2)
-    d_p, _ = time_track(ph, torch, cub, 1, 0, B, reps=2)
+    d_p, r_d = time_track(ph, torch, cub, 1, 0, B, reps=2)
+    d_p["longest_path_alone"] = longest_path_alone(ph, torch, cub, 1, 0, r_d, d_p["seconds"])
+    dd_m["longest_path_alone"] = longest_path_alone(ph, torch, cub, 2, 1, r_m, dd_m["seconds"])
     row = {"double_plain": d_p, "dd_mixed": dd_m, "dd_plain": dd_p,
            "dd_mixed_over_plain": dd_m["paths_per_s"] / dd_p["paths_per_s"],
            "dd_endpoint_agreement_1e-24": endpoint_agreement(ph, r_m, r_p, 8, 2, B, 1e-24)}
@@ -640,6 +668,18 @@ def profile_mode(ph, torch, mode):
         res = ph.track(ph.System(s), synth.gamma_of(s), 6561, ph.track_opts(prec=2, mixed=1))
         print(json.dumps({"mode": mode, "report": res["report"]}))
         return
+    if mode == "track_n8_dd_longest":
+        # the whole workload once (its last dispatch is not the one to read),
+        # then the path with the most steps by itself: the last track_kernel
+        # dispatch of this mode
+        s = synth.tracking_cubic()
+        S, g = ph.System(s), synth.gamma_of(s)
+        opts = ph.track_opts(prec=2, mixed=1)
+        res = ph.track(S, g, 6561, opts)
+        i = int(np.argmax(res["steps"]))
+        one = ph.track(S, g, 1, opts, x_start=ph.start_solutions(S, 2, i, 1))
+        print(json.dumps({"mode": mode, "path": i, "report": one["report"]}))
+        return
     if mode == "track_n16_qd":
         s = synth.tracking_quadratic16()
         res = ph.track(ph.System(s), synth.gamma_of(s), 2 ** 16, ph.track_opts(prec=4, mixed=1))
@@ -670,10 +710,11 @@ def main():
     ap.add_argument("--groups", type=int, default=0,
                     help="with --kernel: equation groups (0: the library's default)")
     ap.add_argument("--mode", default="eval",
-                    choices=["eval", "eval_hbm", "track_n8_dd", "track_n16_qd", "track_batch", "copy"],
+                    choices=["eval", "eval_hbm", "track_n8_dd", "track_n8_dd_longest", "track_n16_qd", "track_batch", "copy"],
                     help="eval: the benchmark line; the others run one workload for profiling: "
                          "the HBM-bound n = 16 evaluation at 2^20 points, the 6561-path DD-mixed "
-                         "tracking of the n = 8 cubic system, the 65536-path QD-mixed "
+                         "tracking of the n = 8 cubic system (or its longest path by itself), "
+                         "the 65536-path QD-mixed "
                          "tracking, the 64-system batch, or a device copy of 2 GiB (calibrates "
                          "the HBM byte counters)")
     args = ap.parse_args()
@@ -843,6 +884,9 @@ def summary(result, L):
     if runs:
         out["track_paths_per_s"] = {k: v["paths_per_s"] for k, v in runs.items()}
         out["track_fp64_frac"] = {k: v["roofline"]["fp64_frac"] for k, v in runs.items() if "roofline" in v}
+        out["track_longest_path_alone_over_whole_run"] = {
+            k: v["longest_path_alone"]["fraction_of_whole_run"] for k, v in runs.items()
+            if "longest_path_alone" in v}
     orc = {"n3_d2_D": ex.get("track_n3_d2_8paths_double", {}).get("oracle"),
            "n8_d3_DD": c.get("oracle"),
            "n16_d2_QD": ex.get("track_n16_d2_qd_mixed_65536paths", {}).get("oracle"),

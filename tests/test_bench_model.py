@@ -120,3 +120,14 @@ def test_summary_keeps_every_cell_last():
     assert out["track_paths_per_s"] == {"n3_d2_8p_D_plain": 3.0}
     assert out["oracle_track_paths_per_s"]["n3_d2_D"] == {"1core": 5.0, "allcores": 9.0, "threads": 2}
     assert out["host"] == {"nproc": 2}
+    assert out["track_longest_path_alone_over_whole_run"] == {}
+
+
+def test_summary_reports_the_longest_path_alone():
+    run = {"paths_per_s": 4.0, "roofline": {"fp64_frac": 0.1},
+           "longest_path_alone": {"path": 7, "steps": 600, "seconds": 0.9, "fraction_of_whole_run": 0.9}}
+    res = {"value": 1.0, "roofline": {"frac": 0.5},
+           "extras": {"track_n8_d3_6561paths": {"dd_mixed": run, "dd_plain": {"paths_per_s": 1.0}}}}
+    out = bench.summary(res, 1)
+    assert out["track_paths_per_s"] == {"n8_d3_6561p_DD_mixed": 4.0, "n8_d3_6561p_DD_plain": 1.0}
+    assert out["track_longest_path_alone_over_whole_run"] == {"n8_d3_6561p_DD_mixed": 0.9}
