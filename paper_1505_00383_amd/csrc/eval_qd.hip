@@ -72,12 +72,14 @@ __device__ __forceinline__ R<4> qd_axpy(const R<4> &r, double e, const R<4> &p)
     return qd_renorm_safe(s0, s1, s2, s3, 0.0);
 }
 
-// the partner lane's value (the other component of the same point)
+// the partner lane's value (the other component of the same point).  Every
+// lane has a source lane in this permutation, so the move carries no "old"
+// operand (which would cost a register set to zero per move)
 __device__ __forceinline__ double pair_swap(double v)
 {
     const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, 0xB1, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), 0xB1, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, 0xB1, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), 0xB1, 0xF, 0xF, true);
     return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
 }
 

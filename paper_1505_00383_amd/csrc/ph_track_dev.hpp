@@ -17,7 +17,9 @@ namespace ph {
 // with one in the other half of its 8- or 16-lane block, as a reduction
 // needs); the step across rows uses a lane permute.  After every step all
 // lanes of a block hold bitwise the same value, because each pair adds the
-// same two operands.
+// same two operands.  Every lane has a source lane in these permutations,
+// so the DPP moves carry no "old" operand (which would cost a register set to
+// zero per move).
 template <int O>
 __device__ __forceinline__ double red_partner(double v)
 {
@@ -26,8 +28,8 @@ __device__ __forceinline__ double red_partner(double v)
     } else {
         constexpr int ctrl = O == 1 ? 0xB1 : (O == 2 ? 0x4E : (O == 4 ? 0x141 : 0x140));
         const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
-        const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, ctrl, 0xF, 0xF, false);
-        const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), ctrl, 0xF, 0xF, false);
+        const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, ctrl, 0xF, 0xF, true);
+        const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), ctrl, 0xF, 0xF, true);
         return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
     }
 }
