@@ -63,9 +63,9 @@ TRAFFIC = {
                     "paper_1505_00383_amd/csrc/ph_internal.hpp": "ab9104fb80a39058"},
     },
     "eval_qd_arow_kernel": {
-        "by_launch": {(3, 4, 1): 169237333 + 4429185621, (3, 4, 2): 296473472 + 4429185579,
-                      (3, 4, 4): 557277269 + 4429185493},
-        "sources": {"paper_1505_00383_amd/csrc/eval_qd.hip": "218895931cd72bc2",
+        "by_launch": {(3, 4, 1): 170525531 + 4429184597, (3, 4, 2): 296279509 + 4429184597,
+                      (3, 4, 4): 558127869 + 4429184597},
+        "sources": {"paper_1505_00383_amd/csrc/eval_qd.hip": "fc3b726e4958d650",
                     "paper_1505_00383_amd/csrc/ph_arow.hpp": "aee6853f608672f7",
                     "paper_1505_00383_amd/csrc/ph_arith.hpp": "1f4274c3666f77a9",
                     "paper_1505_00383_amd/csrc/ph_internal.hpp": "ab9104fb80a39058"},
