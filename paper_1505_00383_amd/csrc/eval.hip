@@ -346,6 +346,7 @@ __device__ __forceinline__ void regrow_fma(RegRow &r, int j, double e, const C<1
 
 // The same row held by the compiler (four indexed planes, see RegRow).
 struct VecRow {
+    static constexpr bool kIndexed = false;  // columns addressed by compile-time index
     RegRow r;
     __device__ __forceinline__ void zero()
     {
@@ -378,6 +379,7 @@ struct VecRow {
 // path requires n_var <= 32).
 #define PH_PIN_CLOBBERS "v128","v129","v130","v131","v132","v133","v134","v135","v136","v137","v138","v139","v140","v141","v142","v143","v144","v145","v146","v147","v148","v149","v150","v151","v152","v153","v154","v155","v156","v157","v158","v159","v160","v161","v162","v163","v164","v165","v166","v167","v168","v169","v170","v171","v172","v173","v174","v175","v176","v177","v178","v179","v180","v181","v182","v183","v184","v185","v186","v187","v188","v189","v190","v191","v192","v193","v194","v195","v196","v197","v198","v199","v200","v201","v202","v203","v204","v205","v206","v207","v208","v209","v210","v211","v212","v213","v214","v215","v216","v217","v218","v219","v220","v221","v222","v223","v224","v225","v226","v227","v228","v229","v230","v231","v232","v233","v234","v235","v236","v237","v238","v239","v240","v241","v242","v243","v244","v245","v246","v247","v248","v249","v250","v251","v252","v253","v254","v255"
 struct PinRow {
+    static constexpr bool kIndexed = true;  // any column by the GPR index mode
     __device__ __forceinline__ void zero()
     {
         asm volatile("v_mov_b64 v[128:129], 0\n\tv_mov_b64 v[130:131], 0\n\tv_mov_b64 v[132:133], 0\n\tv_mov_b64 v[134:135], 0\n\tv_mov_b64 v[136:137], 0\n\tv_mov_b64 v[138:139], 0\n\tv_mov_b64 v[140:141], 0\n\tv_mov_b64 v[142:143], 0\n\tv_mov_b64 v[144:145], 0\n\tv_mov_b64 v[146:147], 0\n\tv_mov_b64 v[148:149], 0\n\tv_mov_b64 v[150:151], 0\n\tv_mov_b64 v[152:153], 0\n\tv_mov_b64 v[154:155], 0\n\tv_mov_b64 v[156:157], 0\n\tv_mov_b64 v[158:159], 0\n\tv_mov_b64 v[160:161], 0\n\tv_mov_b64 v[162:163], 0\n\tv_mov_b64 v[164:165], 0\n\tv_mov_b64 v[166:167], 0\n\tv_mov_b64 v[168:169], 0\n\tv_mov_b64 v[170:171], 0\n\tv_mov_b64 v[172:173], 0\n\tv_mov_b64 v[174:175], 0\n\tv_mov_b64 v[176:177], 0\n\tv_mov_b64 v[178:179], 0\n\tv_mov_b64 v[180:181], 0\n\tv_mov_b64 v[182:183], 0\n\tv_mov_b64 v[184:185], 0\n\tv_mov_b64 v[186:187], 0\n\tv_mov_b64 v[188:189], 0\n\tv_mov_b64 v[190:191], 0\n\tv_mov_b64 v[192:193], 0\n\tv_mov_b64 v[194:195], 0\n\tv_mov_b64 v[196:197], 0\n\tv_mov_b64 v[198:199], 0\n\tv_mov_b64 v[200:201], 0\n\tv_mov_b64 v[202:203], 0\n\tv_mov_b64 v[204:205], 0\n\tv_mov_b64 v[206:207], 0\n\tv_mov_b64 v[208:209], 0\n\tv_mov_b64 v[210:211], 0\n\tv_mov_b64 v[212:213], 0\n\tv_mov_b64 v[214:215], 0\n\tv_mov_b64 v[216:217], 0\n\tv_mov_b64 v[218:219], 0\n\tv_mov_b64 v[220:221], 0\n\tv_mov_b64 v[222:223], 0\n\tv_mov_b64 v[224:225], 0\n\tv_mov_b64 v[226:227], 0\n\tv_mov_b64 v[228:229], 0\n\tv_mov_b64 v[230:231], 0\n\tv_mov_b64 v[232:233], 0\n\tv_mov_b64 v[234:235], 0\n\tv_mov_b64 v[236:237], 0\n\tv_mov_b64 v[238:239], 0\n\tv_mov_b64 v[240:241], 0\n\tv_mov_b64 v[242:243], 0\n\tv_mov_b64 v[244:245], 0\n\tv_mov_b64 v[246:247], 0\n\tv_mov_b64 v[248:249], 0\n\tv_mov_b64 v[250:251], 0\n\tv_mov_b64 v[252:253], 0\n\tv_mov_b64 v[254:255], 0" ::: PH_PIN_CLOBBERS);
@@ -429,6 +431,7 @@ struct PinRow {
 // waves fit each SIMD instead of two.  Same rules as PinRow.
 #define PH_PIN16_CLOBBERS "v64","v65","v66","v67","v68","v69","v70","v71","v72","v73","v74","v75","v76","v77","v78","v79","v80","v81","v82","v83","v84","v85","v86","v87","v88","v89","v90","v91","v92","v93","v94","v95","v96","v97","v98","v99","v100","v101","v102","v103","v104","v105","v106","v107","v108","v109","v110","v111","v112","v113","v114","v115","v116","v117","v118","v119","v120","v121","v122","v123","v124","v125","v126","v127"
 struct PinRow16 {
+    static constexpr bool kIndexed = true;
     __device__ __forceinline__ void zero()
     {
         asm volatile("v_mov_b64 v[64:65], 0\n\tv_mov_b64 v[66:67], 0\n\tv_mov_b64 v[68:69], 0\n\tv_mov_b64 v[70:71], 0\n\tv_mov_b64 v[72:73], 0\n\tv_mov_b64 v[74:75], 0\n\tv_mov_b64 v[76:77], 0\n\tv_mov_b64 v[78:79], 0\n\tv_mov_b64 v[80:81], 0\n\tv_mov_b64 v[82:83], 0\n\tv_mov_b64 v[84:85], 0\n\tv_mov_b64 v[86:87], 0\n\tv_mov_b64 v[88:89], 0\n\tv_mov_b64 v[90:91], 0\n\tv_mov_b64 v[92:93], 0\n\tv_mov_b64 v[94:95], 0\n\tv_mov_b64 v[96:97], 0\n\tv_mov_b64 v[98:99], 0\n\tv_mov_b64 v[100:101], 0\n\tv_mov_b64 v[102:103], 0\n\tv_mov_b64 v[104:105], 0\n\tv_mov_b64 v[106:107], 0\n\tv_mov_b64 v[108:109], 0\n\tv_mov_b64 v[110:111], 0\n\tv_mov_b64 v[112:113], 0\n\tv_mov_b64 v[114:115], 0\n\tv_mov_b64 v[116:117], 0\n\tv_mov_b64 v[118:119], 0\n\tv_mov_b64 v[120:121], 0\n\tv_mov_b64 v[122:123], 0\n\tv_mov_b64 v[124:125], 0\n\tv_mov_b64 v[126:127], 0" ::: PH_PIN16_CLOBBERS);
@@ -647,13 +650,28 @@ __device__ __forceinline__ void dfast_body(const EvalArgs &a, const int32_t *__r
             st_out(&a.val[((int64_t)(i * 2 + 0)) * a.ld + p], v.re.v[0]);
             st_out(&a.val[((int64_t)(i * 2 + 1)) * a.ld + p], v.im.v[0]);
             double *jr = a.jac + (int64_t)i * nv * 2 * a.ld + p;
-#pragma unroll
-            for (int j = 0; j < NC; ++j) {
-                if (j < nv) {
+            if constexpr (Row::kIndexed) {
+                // a loop over the equation's own columns: the register index
+                // is a loop counter, so no per-column bound or offset has to
+                // be kept (an unrolled store kept 64 of them, spilled to
+                // vector-register lanes and read back here)
+                const int64_t ld2 = 2 * a.ld;
+#pragma unroll 1
+                for (int j = 0; j < nv; ++j, jr += ld2) {
                     double re, im;
                     row.get(j, re, im);
-                    st_out(&jr[(int64_t)(j * 2 + 0) * a.ld], re);
-                    st_out(&jr[(int64_t)(j * 2 + 1) * a.ld], im);
+                    st_out(jr, re);
+                    st_out(jr + a.ld, im);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < NC; ++j) {
+                    if (j < nv) {
+                        double re, im;
+                        row.get(j, re, im);
+                        st_out(&jr[(int64_t)(j * 2 + 0) * a.ld], re);
+                        st_out(&jr[(int64_t)(j * 2 + 1) * a.ld], im);
+                    }
                 }
             }
         }
