@@ -7,7 +7,10 @@ assembly and check that no compiler-generated instruction touches the
 pinned registers, that nothing spills to scratch, and that the kernel
 descriptor reserves the pinned registers.  The GPR indexing mode those
 statements use writes M0, which the compiler reserves (a clobber of it is not
-honoured): no compiler-generated instruction of these kernels may use M0."""
+honoured): no compiler-generated instruction of these kernels may use M0.
+Two properties of the compiled code that cost time when lost are checked the
+same way: the pinned row store reads no spilled scalars back, and the QD
+kernel's lane swap sets no zero "old" operand for its DPP moves."""
 import os
 import re
 import shutil
@@ -97,3 +100,45 @@ def test_accumulation_register_row_untouched_by_compiler(asm_acc):
     for b in blocks:
         if "accvgpr" in b and "s_set_gpr_idx_on" in b:
             assert b.strip().split("\n")[-1].strip() == "s_set_gpr_idx_off", b[-200:]
+
+
+def _body(asm, pattern):
+    name = re.search("^(" + pattern + r"\S*):", asm, re.M).group(1)
+    start = asm.index(name + ":")
+    return asm[start:asm.index("; -- End function", start)]
+
+
+def test_row_store_keeps_no_per_column_scalars(asm):
+    """The pinned row leaves in a loop over the equation's columns, so no
+    per-column bound or offset is held in scalar registers across the term
+    loop and spilled to vector-register lanes (an unrolled store read 64 such
+    values back per equation); a few lane spills elsewhere are allowed."""
+    for pattern, _, _ in KERNELS:
+        body = _body(asm, pattern)
+        assert len(re.findall(r"\bv_readlane_b32\b", body)) <= 4, pattern
+
+
+def test_qd_pair_swap_sets_no_zero_old_operand(tmp_path_factory):
+    """Every lane has a source in the QD kernel's adjacent-lane swap, so its DPP
+    moves carry no "old" operand: no DPP move writes a register whose last
+    writer (in program order) set it to zero.  With a zero "old" operand every
+    one of the 2672 moves had such a writer."""
+    body = _body(_compile(tmp_path_factory, "eval_qd.hip"), r"_ZN2ph19eval_qd_arow_kernel")
+    last, moves = {}, 0
+    for ln in body.split("\n"):
+        m = re.match(r"\t(v_\w+)\s+(v\d+|v\[\d+:\d+\])", ln)
+        if not m:
+            continue
+        op, dst = m.group(1), m.group(2)
+        if op == "v_mov_b32_dpp":
+            moves += 1
+            assert last.get(dst) != "zero", ln
+        if dst.startswith("v["):
+            lo, hi = (int(x) for x in dst[2:-1].split(":"))
+            regs = ["v%d" % r for r in range(lo, hi + 1)]
+        else:
+            regs = [dst]
+        kind = "zero" if re.match(r"\tv_mov_b32_e32 v\d+, 0$", ln) else "other"
+        for r in regs:
+            last[r] = kind
+    assert moves > 0
